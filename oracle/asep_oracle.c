@@ -1,0 +1,484 @@
+/*
+ * asep_oracle.c -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, obviously correct CPU reference for the ASEP / KPZ lattice-gas
+ * Monte Carlo of Schulz, Odor, Odor and Nagy, "Simulation of 1+1 dimensional
+ * surface growth and lattice gases using GPUs".  Only tests/, the smoke check
+ * and the cpu_baseline leg of bench.py may load this file.  It shares no code,
+ * header, table or constant generator with the HIP library: every routine is
+ * written here from the paper and from the published Philox definition.
+ *
+ * Storage is one byte per site (0 = hole, 1 = particle); nothing is bit-packed,
+ * blocked or reordered.  Each function names the passage it follows:
+ *
+ *   Sec. 2, Fig. kpzasep      RSOS <-> ASEP mapping: a particle hops to an empty
+ *                             neighbour, right with probability p, left with q.
+ *   Sec. 2.1 (CUDA)           flat start = alternating 1010...; one MCS = every
+ *                             site updated once; parallel sub-lattice updates
+ *                             replace random-sequential ones.  Here the parallel
+ *                             schedule is a randomly shifted domain decomposition
+ *                             (cells of ell sites, random-sequential attempts in
+ *                             each cell, a fresh random shift per sub-sweep).
+ *   Sec. 2.1, Eq. (W)         W^2 = (1/L) sum h^2 - ((1/L) sum h)^2.
+ *   Sec. 2.2, Eq. (sampling)  t_{i+1} = 1.05 t_i, t_0 = 30.
+ *   Sec. 2.3, Eq. (bimodal)   quenched slow sites with p_i = r p (and q_i = r q).
+ *   Sec. 3                    two TASEP lanes with opposite drift and lane
+ *                             changes at randomly chosen turning points.
+ *   Salmon et al., SC'11      Philox4x32-10 counter-based generator.
+ *
+ * The schedule, the Philox counter layout and the threshold lowering are the
+ * readings written down in the design notes; they are restated next to each
+ * routine below.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "asep_oracle.h"
+
+/* ------------------------------------------------------------------------- */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11, Sec. 3 "Philox").        */
+/* Round: two 32x32->64 products of counter words 0 and 2 with the           */
+/* multipliers; the high halves are xored with the other counter words and   */
+/* the key; the key is bumped by the Weyl constants between rounds.          */
+/* ------------------------------------------------------------------------- */
+#define PHX_MUL_A 0xD2511F53u
+#define PHX_MUL_B 0xCD9E8D57u
+#define PHX_WEYL_A 0x9E3779B9u
+#define PHX_WEYL_B 0xBB67AE85u
+
+void orc_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += PHX_WEYL_A;
+            k1 += PHX_WEYL_B;
+        }
+        uint64_t prod_a = (uint64_t)PHX_MUL_A * (uint64_t)c0;
+        uint64_t prod_b = (uint64_t)PHX_MUL_B * (uint64_t)c2;
+        uint32_t n0 = (uint32_t)(prod_b >> 32) ^ c1 ^ k0;
+        uint32_t n1 = (uint32_t)prod_b;
+        uint32_t n2 = (uint32_t)(prod_a >> 32) ^ c3 ^ k1;
+        uint32_t n3 = (uint32_t)prod_a;
+        c0 = n0;
+        c1 = n1;
+        c2 = n2;
+        c3 = n3;
+    }
+    out[0] = c0;
+    out[1] = c1;
+    out[2] = c2;
+    out[3] = c3;
+}
+
+/* Counter tags (top nibble of counter word 2). */
+#define TAG_ATTEMPT 1u
+#define TAG_SHIFT 2u
+#define TAG_INIT 3u
+#define TAG_DIS_P 4u
+#define TAG_DIS_Q 5u
+#define TAG_TURN 6u
+#define TAG_RSU 7u
+
+static void draw(const orc_params *P, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                 uint32_t out[4]) {
+    uint32_t ctr[4] = {c0, c1, c2, c3};
+    uint32_t key[2] = {P->seed, P->stream};
+    orc_philox(ctr, key, out);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Probability -> integer threshold.  "with probability p" (Sec. 2.1) is     */
+/* realised as r < T with r uniform on [0, 2^B):  T(x) = min(2^B,            */
+/* floor(x 2^B)), computed in binary64 (scaling by 2^B and floor are exact). */
+/* ------------------------------------------------------------------------- */
+uint64_t orc_threshold(double x, int bits) {
+    double scaled = floor(ldexp(x, bits));
+    double cap = ldexp(1.0, bits);
+    if (scaled >= cap) return (uint64_t)1 << bits;
+    if (scaled <= 0.0) return 0;
+    return (uint64_t)scaled;
+}
+
+static int is_pow2_log(uint32_t v) { return v >= 1 && v <= 30; }
+
+int orc_lower(const orc_params *P, orc_sched *S) {
+    memset(S, 0, sizeof(*S));
+    if (!is_pow2_log(P->cell_log2)) return -1;
+    uint32_t ell = 1u << P->cell_log2;
+    int two = (P->model == ORC_TWO_LANE);
+    if (P->L < 2 * (uint64_t)ell || P->L % ell != 0) return -1;
+    if (P->subsweeps == 0) return -1;
+    uint32_t per_mcs = two ? 4u * ell : ell; /* attempts per cell per MCS */
+    if (per_mcs % P->subsweeps != 0) return -1;
+    if (!(P->p >= 0 && P->p <= 1 && P->q >= 0 && P->q <= 1)) return -1;
+
+    S->ell = ell;
+    S->lam = P->cell_log2;
+    S->ebits = two ? 2 : 0;
+    S->B = 32 - S->lam - S->ebits;
+    S->a = per_mcs / P->subsweeps;
+    S->S = P->subsweeps;
+
+    /* thresholds at B bits */
+    uint64_t t[5];
+    int nt = 0;
+    if (!two) {
+        S->TB[0] = orc_threshold(P->p, S->B);
+        S->TB[1] = orc_threshold(P->q, S->B);
+        S->TB[2] = orc_threshold(P->slow_factor * P->p, S->B);
+        S->TB[3] = orc_threshold(P->slow_factor * P->q, S->B);
+        t[nt++] = S->TB[0];
+        t[nt++] = S->TB[1];
+        if (P->slow_frac > 0) {
+            t[nt++] = S->TB[2];
+            t[nt++] = S->TB[3];
+        }
+    } else {
+        S->TB[0] = orc_threshold(P->p, S->B);         /* lane A hop right */
+        S->TB[1] = orc_threshold(P->q, S->B);         /* lane B hop left  */
+        S->TB[2] = orc_threshold(P->lane_rate, S->B); /* lane change      */
+        t[nt++] = S->TB[0];
+        t[nt++] = S->TB[1];
+        t[nt++] = S->TB[2];
+    }
+    /* precision b: the fewest low-order bits such that every threshold in use
+     * is an exact multiple of 2^(B-b); then r < T at b bits has the same law. */
+    int b;
+    if (P->rbits < 0) {
+        for (b = 0; b <= (int)S->B; ++b) {
+            int ok = 1;
+            for (int i = 0; i < nt; ++i)
+                if (t[i] % ((uint64_t)1 << (S->B - b)) != 0) ok = 0;
+            if (ok) break;
+        }
+    } else {
+        b = P->rbits;
+        if (b > (int)S->B) return -1;
+        for (int i = 0; i < nt; ++i)
+            if (t[i] % ((uint64_t)1 << (S->B - b)) != 0) return -1;
+    }
+    S->b = (uint32_t)b;
+    for (int i = 0; i < 4; ++i) S->T[i] = S->TB[i] >> (S->B - b);
+    S->w = S->lam + S->ebits + S->b;
+    S->A = 32 / S->w;
+    S->per_block = 4 * S->A;
+    S->T_init = orc_threshold(P->density, 32);
+    S->T_slow = orc_threshold(P->slow_frac, 32);
+    S->T_turn = orc_threshold(P->turn_frac, 32);
+    return 0;
+}
+
+/* Attempt m of cell k in sub-sweep g: block floor(m / 4A), word, slot, then
+ * the field of w bits is split into (j | e | r) from the top. */
+static void attempt_fields(const orc_params *P, const orc_sched *S, uint32_t sample, uint64_t k,
+                           uint64_t g, uint32_t m, uint32_t blockbuf[4], uint32_t *cached_blk,
+                           uint32_t *j, uint32_t *e, uint32_t *r) {
+    uint32_t blk = m / S->per_block;
+    uint32_t q = m % S->per_block;
+    uint32_t wd = q / S->A;
+    uint32_t sl = q % S->A;
+    if (*cached_blk != blk) {
+        uint32_t c2 = (TAG_ATTEMPT << 28) | (blk << 16) | (uint32_t)((g >> 32) & 0xFFFFu);
+        draw(P, (uint32_t)k, (uint32_t)(g & 0xFFFFFFFFu), c2, sample, blockbuf);
+        *cached_blk = blk;
+    }
+    uint32_t u = blockbuf[wd];
+    uint64_t field = ((uint64_t)u >> (sl * S->w)) & ((((uint64_t)1) << S->w) - 1);
+    *r = (uint32_t)(field & ((((uint64_t)1) << S->b) - 1));
+    *e = (uint32_t)((field >> S->b) & ((1u << S->ebits) - 1));
+    *j = (uint32_t)(field >> (S->b + S->ebits));
+}
+
+static uint32_t shift_draw(const orc_params *P, const orc_sched *S, uint32_t sample, uint64_t g) {
+    uint32_t out[4];
+    uint32_t c2 = (TAG_SHIFT << 28) | (uint32_t)((g >> 32) & 0xFFFFu);
+    draw(P, 0, (uint32_t)(g & 0xFFFFFFFFu), c2, sample, out);
+    return out[0] & (S->ell - 1);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Initial state and quenched planes (Sec. 2.1 flat start; Eq. bimodal;      */
+/* Sec. 3 turning points).  A per-site draw uses word (x mod 4) of the block  */
+/* at counter (x / 4, lane, tag << 28, sample or realization).               */
+/* ------------------------------------------------------------------------- */
+static uint32_t site_word(const orc_params *P, uint32_t tag, uint64_t x, uint32_t c1,
+                          uint32_t c3) {
+    uint32_t out[4];
+    draw(P, (uint32_t)(x / 4), c1, tag << 28, c3, out);
+    return out[x % 4];
+}
+
+void orc_init_state(const orc_params *P, const orc_sched *S, uint32_t sample, uint8_t *s) {
+    int planes = P->model == ORC_TWO_LANE ? 2 : 1;
+    for (int lane = 0; lane < planes; ++lane) {
+        uint8_t *st = s + (uint64_t)lane * P->L;
+        for (uint64_t x = 0; x < P->L; ++x) {
+            if (P->init == ORC_INIT_FLAT) {
+                st[x] = (x % 2 == 0) ? 1 : 0;
+            } else {
+                uint32_t u = site_word(P, TAG_INIT, x, (uint32_t)lane, sample);
+                st[x] = ((uint64_t)u < S->T_init) ? 1 : 0;
+            }
+        }
+    }
+}
+
+void orc_init_masks(const orc_params *P, const orc_sched *S, uint32_t realization,
+                    uint8_t *slow_p, uint8_t *slow_q, uint8_t *turn) {
+    for (uint64_t x = 0; x < P->L; ++x) {
+        if (slow_p) slow_p[x] = ((uint64_t)site_word(P, TAG_DIS_P, x, 0, realization) < S->T_slow);
+        if (slow_q) slow_q[x] = ((uint64_t)site_word(P, TAG_DIS_Q, x, 0, realization) < S->T_slow);
+        if (turn) turn[x] = ((uint64_t)site_word(P, TAG_TURN, x, 0, realization) < S->T_turn);
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* One sub-sweep g of the shifted domain decomposition.                      */
+/* sigma = shift draw mod ell; cell k covers sites (sigma + k ell + j) mod L, */
+/* j = 0..ell-1; each cell receives `a` random-sequential attempts.  An      */
+/* attempt picks j; j = ell-1 (the bond leaving the cell) is a no-op.        */
+/* Single lane: "10" at (x, x+1) hops right if r < T_p[x]; "01" hops left if */
+/* r < T_q[x+1] (rates belong to the departure site).                         */
+/* ------------------------------------------------------------------------- */
+static void subsweep_ring(const orc_params *P, const orc_sched *S, uint32_t sample, uint64_t g,
+                          uint8_t *s, const uint8_t *slow_p, const uint8_t *slow_q, int64_t *J) {
+    const uint64_t L = P->L;
+    const uint64_t ncell = L / S->ell;
+    const uint32_t sigma = shift_draw(P, S, sample, g);
+    for (uint64_t k = 0; k < ncell; ++k) {
+        const uint64_t base = (sigma + k * S->ell) % L;
+        uint32_t blockbuf[4];
+        uint32_t cached = 0xFFFFFFFFu;
+        for (uint32_t m = 0; m < S->a; ++m) {
+            uint32_t j, e, r;
+            attempt_fields(P, S, sample, k, g, m, blockbuf, &cached, &j, &e, &r);
+            (void)e;
+            if (j == S->ell - 1) continue;
+            uint64_t x = (base + j) % L;
+            uint64_t y = (x + 1) % L;
+            uint64_t tp = (slow_p && slow_p[x]) ? S->T[2] : S->T[0];
+            uint64_t tq = (slow_q && slow_q[y]) ? S->T[3] : S->T[1];
+            if (s[x] == 1 && s[y] == 0 && (uint64_t)r < tp) {
+                s[x] = 0;
+                s[y] = 1;
+                *J += 1;
+            } else if (s[x] == 0 && s[y] == 1 && (uint64_t)r < tq) {
+                s[x] = 1;
+                s[y] = 0;
+                *J -= 1;
+            }
+        }
+    }
+}
+
+/* Two lanes (Sec. 3): lane A hops right, lane B hops left, and a particle may
+ * change lane at a turning point when the other lane's site is empty.  The
+ * event e of each attempt is 0: A hop on bond (x,x+1); 1: B hop on bond
+ * (x,x+1) from x+1 to x; 2: A->B at x; 3: B->A at x.  Bond events with
+ * j = ell-1 are no-ops; site events use every j. */
+static void subsweep_two_lane(const orc_params *P, const orc_sched *S, uint32_t sample, uint64_t g,
+                              uint8_t *s, const uint8_t *turn, int64_t *J) {
+    const uint64_t L = P->L;
+    uint8_t *A = s;
+    uint8_t *Bl = s + L;
+    const uint64_t ncell = L / S->ell;
+    const uint32_t sigma = shift_draw(P, S, sample, g);
+    for (uint64_t k = 0; k < ncell; ++k) {
+        const uint64_t base = (sigma + k * S->ell) % L;
+        uint32_t blockbuf[4];
+        uint32_t cached = 0xFFFFFFFFu;
+        for (uint32_t m = 0; m < S->a; ++m) {
+            uint32_t j, e, r;
+            attempt_fields(P, S, sample, k, g, m, blockbuf, &cached, &j, &e, &r);
+            uint64_t x = (base + j) % L;
+            uint64_t y = (x + 1) % L;
+            if (e == 0) {
+                if (j != S->ell - 1 && A[x] == 1 && A[y] == 0 && (uint64_t)r < S->T[0]) {
+                    A[x] = 0;
+                    A[y] = 1;
+                    *J += 1;
+                }
+            } else if (e == 1) {
+                if (j != S->ell - 1 && Bl[y] == 1 && Bl[x] == 0 && (uint64_t)r < S->T[1]) {
+                    Bl[y] = 0;
+                    Bl[x] = 1;
+                    *J -= 1;
+                }
+            } else if (e == 2) {
+                if (turn[x] && A[x] == 1 && Bl[x] == 0 && (uint64_t)r < S->T[2]) {
+                    A[x] = 0;
+                    Bl[x] = 1;
+                }
+            } else {
+                if (turn[x] && Bl[x] == 1 && A[x] == 0 && (uint64_t)r < S->T[2]) {
+                    Bl[x] = 0;
+                    A[x] = 1;
+                }
+            }
+        }
+    }
+}
+
+void orc_sweep(const orc_params *P, const orc_sched *S, uint32_t sample, uint8_t *s,
+               const uint8_t *mask_a, const uint8_t *mask_b, uint64_t t0, uint64_t n_mcs,
+               int64_t *J) {
+    for (uint64_t t = t0; t < t0 + n_mcs; ++t) {
+        for (uint32_t sub = 0; sub < S->S; ++sub) {
+            uint64_t g = t * S->S + sub;
+            if (P->model == ORC_TWO_LANE)
+                subsweep_two_lane(P, S, sample, g, s, mask_a, J);
+            else
+                subsweep_ring(P, S, sample, g, s, mask_a, mask_b, J);
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Heights and roughness (Sec. 2.1, Eq. W).  h_0 = 0 and                      */
+/* h_{x+1} = h_x + 1 - 2 s_x, so "10" is a local minimum and a right hop      */
+/* deposits.  S1 = sum_x h_x and S2 = sum_x h_x^2 over x = 0..L-1, exact.     */
+/* ------------------------------------------------------------------------- */
+void orc_sums(const uint8_t *s, uint64_t L, int64_t *S1, uint64_t *S2_lo, int64_t *S2_hi,
+              int64_t *N) {
+    __int128 s1 = 0, s2 = 0;
+    int64_t h = 0, n = 0;
+    for (uint64_t x = 0; x < L; ++x) {
+        s1 += h;
+        s2 += (__int128)h * h;
+        h += 1 - 2 * (int64_t)s[x];
+        n += s[x];
+    }
+    *S1 = (int64_t)s1;
+    *S2_lo = (uint64_t)(unsigned __int128)s2;
+    *S2_hi = (int64_t)(s2 >> 64);
+    *N = n;
+}
+
+/* W^2 = (L S2 - S1^2) / L^2: the numerator is exact in 128-bit integers and
+ * converted once. */
+double orc_w2(uint64_t L, int64_t S1, uint64_t S2_lo, int64_t S2_hi) {
+    __int128 s2 = ((__int128)S2_hi << 64) | (__int128)S2_lo;
+    __int128 num = (__int128)L * s2 - (__int128)S1 * S1;
+    return (double)num / ((double)L * (double)L);
+}
+
+/* Full run of one sample: init, then for each requested time t (ascending,
+ * t = 0 meaning the initial state) advance to t and record (S1, S2, J, N). */
+int orc_run(const orc_params *P, uint32_t sample, const uint64_t *times, uint32_t n_times,
+            orc_record *rec, uint8_t *final_state) {
+    orc_sched S;
+    if (orc_lower(P, &S) != 0) return -1;
+    int planes = P->model == ORC_TWO_LANE ? 2 : 1;
+    uint8_t *s = (uint8_t *)calloc((size_t)P->L * planes, 1);
+    uint8_t *ma = NULL, *mb = NULL;
+    uint32_t spd = P->samples_per_disorder ? P->samples_per_disorder : 1;
+    uint32_t realization = sample / spd;
+    if (!s) return -2;
+    orc_init_state(P, &S, sample, s);
+    if (P->model == ORC_TWO_LANE) {
+        ma = (uint8_t *)calloc(P->L, 1);
+        orc_init_masks(P, &S, realization, NULL, NULL, ma);
+    } else if (P->slow_frac > 0) {
+        ma = (uint8_t *)calloc(P->L, 1);
+        if (P->q > 0) mb = (uint8_t *)calloc(P->L, 1);
+        orc_init_masks(P, &S, realization, ma, mb, NULL);
+    }
+    int64_t J = 0;
+    uint64_t t = 0;
+    for (uint32_t i = 0; i < n_times; ++i) {
+        if (times[i] < t) {
+            free(s);
+            free(ma);
+            free(mb);
+            return -1;
+        }
+        orc_sweep(P, &S, sample, s, ma, mb, t, times[i] - t, &J);
+        t = times[i];
+        orc_sums(s, P->L, &rec[i].S1, &rec[i].S2_lo, &rec[i].S2_hi, &rec[i].N);
+        if (P->model == ORC_TWO_LANE) {
+            int64_t nb = 0;
+            for (uint64_t x = 0; x < P->L; ++x) nb += s[P->L + x];
+            rec[i].N += nb;
+        }
+        rec[i].J = J;
+    }
+    if (final_state) memcpy(final_state, s, (size_t)P->L * planes);
+    free(s);
+    free(ma);
+    free(mb);
+    return 0;
+}
+
+/* Continue a run from a given state (checkpoint/resume and chunk checks). */
+int orc_advance(const orc_params *P, uint32_t sample, uint8_t *s, uint64_t t0, uint64_t n_mcs,
+                int64_t *J) {
+    orc_sched S;
+    if (orc_lower(P, &S) != 0) return -1;
+    uint8_t *ma = NULL, *mb = NULL;
+    uint32_t spd = P->samples_per_disorder ? P->samples_per_disorder : 1;
+    uint32_t realization = sample / spd;
+    if (P->model == ORC_TWO_LANE) {
+        ma = (uint8_t *)calloc(P->L, 1);
+        orc_init_masks(P, &S, realization, NULL, NULL, ma);
+    } else if (P->slow_frac > 0) {
+        ma = (uint8_t *)calloc(P->L, 1);
+        if (P->q > 0) mb = (uint8_t *)calloc(P->L, 1);
+        orc_init_masks(P, &S, realization, ma, mb, NULL);
+    }
+    orc_sweep(P, &S, sample, s, ma, mb, t0, n_mcs, J);
+    free(ma);
+    free(mb);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Random-sequential update (Sec. 2.1: the serial dynamics the parallel       */
+/* update is compared with).  One MCS = L attempts; each picks a bond         */
+/* (x, x+1) uniformly (word 0 of its own Philox block, x = floor(u L / 2^32)) */
+/* and accepts with 32-bit thresholds from word 1.                           */
+/* ------------------------------------------------------------------------- */
+int orc_rsu(const orc_params *P, uint32_t sample, uint8_t *s, uint64_t t0, uint64_t n_mcs,
+            int64_t *J) {
+    uint64_t L = P->L;
+    uint64_t tp = orc_threshold(P->p, 32), tq = orc_threshold(P->q, 32);
+    for (uint64_t t = t0; t < t0 + n_mcs; ++t) {
+        for (uint64_t i = 0; i < L; ++i) {
+            uint64_t n = t * L + i;
+            uint32_t out[4];
+            draw(P, (uint32_t)n, (uint32_t)(n >> 32), TAG_RSU << 28, sample, out);
+            uint64_t x = ((uint64_t)out[0] * L) >> 32;
+            uint64_t y = (x + 1) % L;
+            if (s[x] == 1 && s[y] == 0 && (uint64_t)out[1] < tp) {
+                s[x] = 0;
+                s[y] = 1;
+                *J += 1;
+            } else if (s[x] == 0 && s[y] == 1 && (uint64_t)out[1] < tq) {
+                s[x] = 1;
+                s[y] = 0;
+                *J -= 1;
+            }
+        }
+    }
+    return 0;
+}
+
+/* Sampling times of Eq. (sampling): t_0 = 30, t_{i+1} = 1.05 t_i with real t;
+ * a sample is taken at ceil(t_i) for every t_i <= t_max, preceded by t = 0. */
+uint32_t orc_sample_times(double t0, double factor, uint64_t t_max, uint64_t *out, uint32_t cap) {
+    uint32_t n = 0;
+    if (cap > 0) out[n++] = 0;
+    double t = t0;
+    while (t <= (double)t_max) {
+        uint64_t c = (uint64_t)ceil(t);
+        if (c > t_max) break;
+        if (n == 0 || out[n - 1] != c) {
+            if (n >= cap) break;
+            out[n++] = c;
+        }
+        t = t * factor;
+    }
+    return n;
+}
