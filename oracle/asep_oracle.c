@@ -192,11 +192,14 @@ static void attempt_fields(const orc_params *P, const orc_sched *S, uint32_t sam
     *j = (uint32_t)(field >> (S->b + S->ebits));
 }
 
+/* The shift of sub-sweep g is word (g mod 4) of the block at counter
+ * (0, lo32(g/4), SHIFT << 28 | hi16(g/4), sample), reduced mod ell. */
 static uint32_t shift_draw(const orc_params *P, const orc_sched *S, uint32_t sample, uint64_t g) {
     uint32_t out[4];
-    uint32_t c2 = (TAG_SHIFT << 28) | (uint32_t)((g >> 32) & 0xFFFFu);
-    draw(P, 0, (uint32_t)(g & 0xFFFFFFFFu), c2, sample, out);
-    return out[0] & (S->ell - 1);
+    uint64_t quad = g / 4;
+    uint32_t c2 = (TAG_SHIFT << 28) | (uint32_t)((quad >> 32) & 0xFFFFu);
+    draw(P, 0, (uint32_t)(quad & 0xFFFFFFFFu), c2, sample, out);
+    return out[g % 4] % S->ell;
 }
 
 /* ------------------------------------------------------------------------- */

@@ -1,0 +1,198 @@
+"""Python front end of the C ABI: one ``Simulation`` per asep_sim handle.
+
+Device buffers come from PyTorch (``torch.empty(..., device="cuda")``) and are
+handed to ``asep_create_ext`` together with torch's current HIP stream; every
+step of the simulation runs in the HIP library.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import binding as B
+
+
+def make_params(L: int, samples: int = 1, *, model: int = B.ASEP_MODEL_RING,
+                init: int = B.ASEP_INIT_FLAT, density: float = 0.5, p: float = 1.0,
+                q: float = 0.0, slow_frac: float = 0.0, slow_factor: float = 1.0,
+                samples_per_disorder: int = 1, lane_rate: float = 0.0, turn_frac: float = 0.0,
+                seed: int = 1, stream: int = 0, cell_log2: int = 0, subsweeps: int = 0,
+                rbits: int = -1, sample_offset: int = 0) -> B.asep_params:
+    P = B.asep_params()
+    P.abi_version = B.ASEP_ABI_VERSION
+    P.model = model
+    P.L = L
+    P.samples = samples
+    P.sample_offset = sample_offset
+    P.init = init
+    P.samples_per_disorder = samples_per_disorder
+    P.density = density
+    P.p = p
+    P.q = q
+    P.slow_frac = slow_frac
+    P.slow_factor = slow_factor
+    P.lane_rate = lane_rate
+    P.turn_frac = turn_frac
+    P.seed = seed & 0xFFFFFFFF
+    P.stream = stream & 0xFFFFFFFF
+    P.cell_log2 = cell_log2
+    P.subsweeps = subsweeps
+    P.rbits = rbits
+    return P
+
+
+@dataclass
+class Rough:
+    """Measurements of one time: per-sample exact sums and W^2."""
+
+    S1: np.ndarray     # int64 [samples]
+    S2: list           # python ints [samples]
+    J: np.ndarray      # int64 [samples]
+    N: np.ndarray      # int64 [samples]
+    w2: np.ndarray     # float64 [samples]
+
+
+def _rough_arrays(arr, n: int) -> Rough:
+    S1 = np.array([arr[i].sum_h for i in range(n)], dtype=np.int64)
+    S2 = [(int(arr[i].sum_h2_hi) << 64) + int(arr[i].sum_h2_lo) for i in range(n)]
+    J = np.array([arr[i].hops for i in range(n)], dtype=np.int64)
+    N = np.array([arr[i].particles for i in range(n)], dtype=np.int64)
+    w2 = np.array([arr[i].w2 for i in range(n)], dtype=np.float64)
+    return Rough(S1, S2, J, N, w2)
+
+
+class Simulation:
+    """An ensemble of rings on the GPU (asep_create_ext with torch buffers)."""
+
+    def __init__(self, params: B.asep_params, *, buffers: str = "torch", device: int = 0):
+        lib = B.load()
+        self.params_in = params
+        self._h = ctypes.c_void_p()
+        if buffers == "torch":
+            import torch
+
+            sb = ctypes.c_size_t()
+            ab = ctypes.c_size_t()
+            B.check(lib.asep_buffer_sizes(ctypes.byref(params), ctypes.byref(sb),
+                                          ctypes.byref(ab)), "asep_buffer_sizes")
+            dev = torch.device("cuda", device)
+            self.state_buf = torch.empty(max(sb.value, 8), dtype=torch.uint8, device=dev)
+            self.aux_buf = torch.empty(max(ab.value, 8), dtype=torch.uint8, device=dev)
+            self.torch_stream = torch.cuda.current_stream(dev)
+            B.check(lib.asep_create_ext(ctypes.byref(params), self.state_buf.data_ptr(), sb.value,
+                                        self.aux_buf.data_ptr(), ab.value,
+                                        self.torch_stream.cuda_stream, ctypes.byref(self._h)),
+                    "asep_create_ext")
+        elif buffers == "library":
+            B.check(lib.asep_create(ctypes.byref(params), ctypes.byref(self._h)), "asep_create")
+        else:
+            raise ValueError(buffers)
+        self.params = B.asep_params()
+        B.check(lib.asep_get_params(self._h, ctypes.byref(self.params)), "asep_get_params")
+        self.L = int(self.params.L)
+        self.samples = int(self.params.samples)
+        self.planes = 2 if self.params.model == B.ASEP_MODEL_TWO_LANE else 1
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def time(self) -> int:
+        return int(B.load().asep_time(self._h))
+
+    def sweep(self, n_mcs: int) -> None:
+        B.check(B.load().asep_sweep(self._h, int(n_mcs)), "asep_sweep")
+
+    def roughness(self) -> Rough:
+        arr = (B.asep_rough * self.samples)()
+        B.check(B.load().asep_roughness(self._h, arr), "asep_roughness")
+        return _rough_arrays(arr, self.samples)
+
+    def run(self, times) -> list:
+        times = [int(t) for t in times]
+        n = len(times)
+        tarr = (ctypes.c_uint64 * max(n, 1))(*times)
+        arr = (B.asep_rough * max(n * self.samples, 1))()
+        B.check(B.load().asep_run(self._h, tarr, n, arr), "asep_run")
+        out = []
+        for i in range(n):
+            sub = (B.asep_rough * self.samples).from_address(
+                ctypes.addressof(arr) + i * self.samples * ctypes.sizeof(B.asep_rough))
+            out.append(_rough_arrays(sub, self.samples))
+        return out
+
+    def read_state(self, sample: int) -> np.ndarray:
+        n = self.planes * self.L // 64
+        out = np.zeros(n, dtype=np.uint64)
+        B.check(B.load().asep_read_state(self._h, sample,
+                                         out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), n),
+                "asep_read_state")
+        return out
+
+    def write_state(self, sample: int, words: np.ndarray) -> None:
+        w = np.ascontiguousarray(words, dtype=np.uint64)
+        B.check(B.load().asep_write_state(self._h, sample,
+                                          w.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                          w.size), "asep_write_state")
+
+    def read_mask(self, plane: int, realization: int) -> np.ndarray:
+        out = np.zeros(self.L // 64, dtype=np.uint64)
+        B.check(B.load().asep_read_mask(self._h, plane, realization,
+                                        out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                        out.size), "asep_read_mask")
+        return out
+
+    def current(self) -> np.ndarray:
+        out = np.zeros(self.samples, dtype=np.int64)
+        B.check(B.load().asep_current(self._h,
+                                      out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))),
+                "asep_current")
+        return out
+
+    def set_time(self, t: int, hops=None) -> None:
+        ptr = None
+        if hops is not None:
+            h = np.ascontiguousarray(hops, dtype=np.int64)
+            ptr = h.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        B.check(B.load().asep_set_time(self._h, int(t), ptr), "asep_set_time")
+
+    def close(self) -> None:
+        if self._h:
+            B.load().asep_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def sample_times(t0: float, factor: float, t_max: int, cap: int = 100000) -> list:
+    out = (ctypes.c_uint64 * cap)()
+    n = ctypes.c_uint32()
+    B.check(B.load().asep_sample_times(float(t0), float(factor), int(t_max), out, cap,
+                                       ctypes.byref(n)), "asep_sample_times")
+    return [int(out[i]) for i in range(n.value)]
+
+
+def ensemble_w2(rough_list, L: int) -> float:
+    """Order-independent ensemble W^2 from exact sums (asep_ensemble_w2)."""
+    n = len(rough_list.S1)
+    arr = (B.asep_rough * n)()
+    for i in range(n):
+        arr[i].sum_h = int(rough_list.S1[i])
+        arr[i].sum_h2_lo = rough_list.S2[i] & ((1 << 64) - 1)
+        arr[i].sum_h2_hi = rough_list.S2[i] >> 64
+    out = ctypes.c_double()
+    B.check(B.load().asep_ensemble_w2(arr, n, L, ctypes.byref(out)), "asep_ensemble_w2")
+    return out.value

@@ -1,0 +1,227 @@
+"""Bit-exact parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Words of the final state, and S1, S2, J, N at every measurement time, must
+be identical; W^2 formed from them must agree to 1e-12 relative.  Cases span
+several workgroup tiles, ragged ring lengths and packings, every cell size
+and sub-sweep count the kernels accept, the dyadic (packed) and general
+threshold encodings, quenched disorder, two lanes, and prefixes of the
+benchmark workloads at their full ring sizes.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+import paper_1012_0385_amd as A  # noqa: E402
+from paper_1012_0385_amd import binding as B  # noqa: E402
+
+
+def oracle_params(orc, kw):
+    """The same run parameters in the oracle's own structure."""
+    return orc.Params(
+        L=kw["L"], model=kw.get("model", 0), init=kw.get("init", 0),
+        density=kw.get("density", 0.5), p=kw.get("p", 1.0), q=kw.get("q", 0.0),
+        slow_frac=kw.get("slow_frac", 0.0), slow_factor=kw.get("slow_factor", 1.0),
+        samples_per_disorder=kw.get("samples_per_disorder", 1),
+        lane_rate=kw.get("lane_rate", 0.0), turn_frac=kw.get("turn_frac", 0.0),
+        seed=kw.get("seed", 1), stream=kw.get("stream", 0),
+        cell_log2=kw.get("cell_log2", 6) or 6, subsweeps=kw.get("subsweeps", 4) or 4,
+        rbits=kw.get("rbits", -1))
+
+
+def compare(orc, kw, times, samples, check_states=True, buffers="torch"):
+    print("case:", kw, "times", times[:4], "...", len(times), "samples", samples, flush=True)
+    P = A.make_params(samples=samples, **kw)
+    sim = A.Simulation(P, buffers=buffers)
+    got = sim.run(times)
+    OP = oracle_params(orc, kw)
+    off = kw.get("sample_offset", 0)
+    for i in range(samples):
+        ref = orc.run(OP, off + i, times)
+        for ti in range(len(times)):
+            g = got[ti]
+            assert g.S1[i] == ref.S1[ti], ("S1", i, times[ti])
+            assert g.S2[i] == ref.S2[ti], ("S2", i, times[ti])
+            assert g.J[i] == ref.J[ti], ("J", i, times[ti])
+            assert g.N[i] == ref.N[ti], ("N", i, times[ti])
+            w = orc.w2(kw["L"], int(ref.S1[ti]), ref.S2[ti])
+            assert abs(g.w2[i] - w) <= 1e-12 * max(abs(w), 1e-300)
+        if check_states:
+            words = sim.read_state(i)
+            assert np.array_equal(words, orc.pack_words(ref.state)), ("state", i)
+    sim.close()
+    return got
+
+
+def test_flat_start_and_config1(orc):
+    # plain ring, L = 4096, 8 samples, p = 1, q = 0, flat start, 1000 MCS,
+    # measured at t = 0 and powers of two
+    times = [0] + [2**k for k in range(10)] + [1000]
+    got = compare(orc, dict(L=4096, p=1.0, q=0.0, seed=1, stream=1), times, 8)
+    assert np.all(got[0].w2 == 0.25)
+
+
+@pytest.mark.parametrize("L,cell_log2,S,p,q", [
+    (128, 6, 4, 1.0, 0.0),       # two cells, one word per lane
+    (192, 6, 1, 0.5, 0.5),       # three words, ragged
+    (640, 6, 16, 0.8, 0.1),      # general thresholds (one attempt per 32 bits)
+    (4160, 6, 64, 0.75, 0.25),   # ragged 65-word ring
+    (64, 5, 2, 1.0, 0.0),        # one word: a lane is its own neighbour
+    (1024, 5, 8, 0.6, 0.3),
+    (2048, 4, 4, 1.0, 0.5),
+    (512, 3, 1, 0.9, 0.0),
+    (256, 1, 2, 0.7, 0.2),       # two-site cells
+    (65600, 6, 4, 1.0, 0.0),     # 1025 words: C = 2 with a ragged last lane
+])
+def test_plain_shapes(orc, L, cell_log2, S, p, q):
+    compare(orc, dict(L=L, cell_log2=cell_log2, subsweeps=S, p=p, q=q, seed=7, stream=3,
+                      init=1, density=0.4), [0, 1, 5, 12], 3)
+
+
+def test_many_rings_per_workgroup(orc):
+    # 37 rings of 2 words: packed 128 per workgroup, last workgroup partial
+    compare(orc, dict(L=128, p=0.8, q=0.3, seed=5, stream=9), [0, 3, 40], 37)
+    compare(orc, dict(L=320, p=1.0, q=0.0, seed=5, stream=9, sample_offset=1000), [0, 30], 70)
+
+
+def test_disorder(orc):
+    kw = dict(L=4096, p=1.0, q=0.0, slow_frac=0.1, slow_factor=0.5, samples_per_disorder=4,
+              seed=3, stream=2)
+    compare(orc, kw, [0, 4, 33], 8)
+    kw = dict(L=2048, p=0.75, q=0.5, slow_frac=0.3, slow_factor=0.25, samples_per_disorder=2,
+              seed=3, stream=2, sample_offset=5, subsweeps=16)
+    compare(orc, kw, [0, 9, 20], 5)
+
+
+def test_disorder_masks_match_oracle(orc):
+    kw = dict(L=4096, p=0.75, q=0.5, slow_frac=0.1, slow_factor=0.5, samples_per_disorder=4,
+              seed=3, stream=2, sample_offset=6)
+    sim = A.Simulation(A.make_params(samples=7, **kw))
+    OP = oracle_params(orc, kw)
+    for real in (1, 2, 3):
+        sp, sq, _ = orc.init_masks(OP, real)
+        assert np.array_equal(sim.read_mask(0, real), orc.pack_words(sp))
+        assert np.array_equal(sim.read_mask(1, real), orc.pack_words(sq))
+    sim.close()
+
+
+@pytest.mark.parametrize("L,S,lane_rate,turn", [(1024, 4, 0.1, 0.05), (256, 16, 0.25, 0.5),
+                                                 (4160, 1, 0.5, 0.3)])
+def test_two_lane(orc, L, S, lane_rate, turn):
+    kw = dict(L=L, model=1, init=1, density=0.3, p=1.0, q=1.0, lane_rate=lane_rate,
+              turn_frac=turn, subsweeps=S, seed=11, stream=4)
+    compare(orc, kw, [0, 2, 15], 5)
+
+
+def test_two_lane_general_rates(orc):
+    kw = dict(L=512, model=1, init=1, density=0.5, p=0.7, q=0.4, lane_rate=0.1,
+              turn_frac=0.2, seed=2, stream=8)
+    compare(orc, kw, [0, 6], 4)
+
+
+def test_chunks_and_roughness_agree(orc):
+    kw = dict(L=2048, p=0.5, q=0.5, seed=9, stream=1)
+    P = A.make_params(samples=4, **kw)
+    s1 = A.Simulation(P)
+    s1.sweep(5)
+    s1.sweep(7)
+    r1 = s1.roughness()
+    s2 = A.Simulation(P)
+    r2 = s2.run([12])[0]
+    assert np.array_equal(r1.S1, r2.S1) and r1.S2 == r2.S2 and np.array_equal(r1.J, r2.J)
+    for i in range(4):
+        assert np.array_equal(s1.read_state(i), s2.read_state(i))
+    s1.close()
+    s2.close()
+
+
+def test_library_buffers_equal_borrowed(orc):
+    kw = dict(L=1024, p=0.9, q=0.2, seed=4, stream=4)
+    a = compare(orc, kw, [0, 10], 3, buffers="library")
+    b = compare(orc, kw, [0, 10], 3, buffers="torch")
+    assert np.array_equal(a[1].S1, b[1].S1)
+
+
+def test_checkpoint_resume(orc):
+    kw = dict(L=1024, p=0.8, q=0.1, seed=6, stream=2)
+    P = A.make_params(samples=2, **kw)
+    sim = A.Simulation(P)
+    sim.sweep(9)
+    words = [sim.read_state(i) for i in range(2)]
+    hops = sim.current()
+    sim.sweep(6)
+    want = [sim.read_state(i) for i in range(2)]
+    sim2 = A.Simulation(P)
+    for i in range(2):
+        sim2.write_state(i, words[i])
+    sim2.set_time(9, hops)
+    sim2.sweep(6)
+    for i in range(2):
+        assert np.array_equal(sim2.read_state(i), want[i])
+    assert np.array_equal(sim2.current(), sim.current())
+    # a state written from the host continues like the oracle from that state
+    OP = oracle_params(orc, kw)
+    st = orc.unpack_words(words[1])
+    J = orc.advance(OP, 1, st, 9, 6, int(hops[1]))
+    assert np.array_equal(orc.pack_words(st), want[1]) and J == sim.current()[1]
+    sim.close()
+    sim2.close()
+
+
+def test_sampling_times_match_oracle(orc):
+    assert A.sample_times(30, 1.05, 10**7) == orc.sample_times(30, 1.05, 10**7)
+    assert A.sample_times(30, 1.05, 10**5) == orc.sample_times(30, 1.05, 10**5)
+
+
+def test_ensemble_w2_matches_mean():
+    P = A.make_params(samples=6, L=1024, p=1.0, q=0.0)
+    sim = A.Simulation(P)
+    r = sim.run([0, 50])[1]
+    ens = A.ensemble_w2(r, 1024)
+    assert abs(ens - r.w2.mean()) <= 1e-12 * ens
+    sim.close()
+
+
+# --------------------------------------------------------------------------- workload prefixes
+def test_kpz_ew_rings_2p17_prefix(orc):
+    # the LDS-resident workload's ring size: L = 2^17, flat start, KPZ and EW
+    for stream, (p, q) in ((0, (1.0, 0.0)), (1, (0.5, 0.5))):
+        compare(orc, dict(L=1 << 17, p=p, q=q, seed=1, stream=stream), [0, 1, 8, 20], 3)
+
+
+def test_columnar_disorder_2p16_prefix(orc):
+    kw = dict(L=1 << 16, p=1.0, q=0.0, slow_frac=0.1, slow_factor=0.5, samples_per_disorder=4,
+              seed=1, stream=2)
+    compare(orc, kw, [0, 5, 12], 8)
+
+
+def test_two_lane_2p16_prefix(orc):
+    kw = dict(L=1 << 16, model=1, init=1, density=0.3, p=1.0, q=1.0, lane_rate=0.1,
+              turn_frac=0.05, seed=1, stream=3)
+    compare(orc, kw, [0, 3, 6], 3)
+
+
+def test_largest_register_ring(orc):
+    # 2^19 sites: 16 slots per lane, 512 lanes
+    compare(orc, dict(L=1 << 19, p=1.0, q=0.0, seed=2, stream=5), [0, 2], 1)
+
+
+def test_invalid_parameters_rejected():
+    lib = B.load()
+    bad = [dict(L=100), dict(L=64, cell_log2=6), dict(L=1024, p=1.5), dict(L=1024, subsweeps=3),
+           dict(L=1024, model=1, slow_frac=0.1)]
+    for kw in bad:
+        P = A.make_params(samples=1, **kw)
+        import ctypes
+        h = ctypes.c_void_p()
+        assert lib.asep_create(ctypes.byref(P), ctypes.byref(h)) < 0
+        assert not h.value

@@ -409,11 +409,13 @@ def test_ew_saturation_width(orc):
     assert abs(vals.mean() - (L + 1) / 12) < 5 * vals.std() / np.sqrt(len(vals)) + 0.05
 
 
-def _growth_slope(orc, p, q, L=8192, t_hi=3000, n=6):
+def _growth_slope(orc, p, q, L=8192, t_hi=3000, n=16):
+    from concurrent.futures import ThreadPoolExecutor
+
     times = orc.sample_times(30, 1.05, t_hi)
-    W = []
-    for smp in range(n):
-        W.append(orc.run(orc.Params(L=L, p=p, q=q), smp, times).w2(L))
+    P = orc.Params(L=L, p=p, q=q)
+    with ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
+        W = list(ex.map(lambda smp: orc.run(P, smp, times).w2(L), range(n)))
     W = np.mean(W, axis=0) - 0.25  # subtract the intrinsic width (Sec. 2.2)
     t = np.array(times[1:], dtype=float)
     sel = t >= 100
