@@ -1,0 +1,186 @@
+#!/usr/bin/env python
+"""Benchmark of the ASEP / KPZ sweep on one MI355X.
+
+Workload (the LDS-resident ring configuration): rings of L = 2^17 sites,
+half filled, flat start, KPZ (p = 1, q = 0) and EW (p = q = 1/2) with 64
+samples each, 10^5 MCS, W^2 measured at t = 0 and at the geometric times of
+Eq. (sampling) (t_0 = 30, factor 1.05: 168 measurements).  One step = one
+such job: reset of both ensembles (init kernels) and their full runs.
+
+Two forms are timed: "plain" runs the two ensembles one after the other
+(one run per launch sequence); "batched" runs them concurrently on two
+streams.  value = elementary update attempts (site updates) per second of
+the batched form.
+
+The JSON line also carries the ALU roofline of the dominant kernel (the
+sweep kernel: per-launch algorithmic instruction slots over its average
+duration from HIP events on its own stream) and the CPU oracle timed on
+the host cores over a bounded prefix of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import threading
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+L = 1 << 17
+SAMPLES = 64
+T_MAX = 100_000
+MODELS = (("kpz", 1.0, 0.0, 0), ("ew", 0.5, 0.5, 1))  # name, p, q, stream id
+PEAK_SLOTS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock: 32-bit VALU slots/s
+PHILOX_SLOTS = 100  # 10 rounds x (2 quarter-rate 32x32->64 products + 2 xor3)
+UPDATE_SLOTS = 10   # field extraction, pair test, thresholds, flip, hop count
+
+
+def alu_slots_per_attempt(sim):
+    """Algorithmic 32-bit VALU slots per attempt for a simulation's schedule."""
+    p = sim.params
+    ell = 1 << p.cell_log2
+    a = ell // p.subsweeps
+    w = p.cell_log2 + p.rbits
+    per_word = 32 // w
+    nblk = -(-a // (4 * per_word))
+    return PHILOX_SLOTS * nblk / a + UPDATE_SLOTS
+
+
+def cpu_baseline(times_all, n_rings, t_cut):
+    """The oracle on a prefix: n_rings per model for t_cut MCS, on host threads."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle
+
+    oracle.build()
+    threads = min(os.cpu_count() or 1, 16)
+    times = [t for t in times_all if t <= t_cut]
+    if times[-1] != t_cut:
+        times.append(t_cut)
+    jobs = []
+    for name, p, q, sid in MODELS:
+        P = oracle.Params(L=L, p=p, q=q, seed=1, stream=sid)
+        jobs += [(P, i) for i in range(n_rings)]
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(lambda j: oracle.run(j[0], j[1], times), jobs))
+    dt = time.perf_counter() - t0
+    attempts = len(jobs) * L * t_cut
+    return {"value": attempts / dt, "unit": "site-updates/s", "cores": threads, "kind": "oracle",
+            "sample": "%d rings (KPZ and EW, %d each) of L=2^17 for the first %d of 10^5 MCS "
+                      "with the same measurement times; %.1f s wall" % (len(jobs), n_rings, t_cut, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--cpu-rings", type=int, default=16)
+    ap.add_argument("--cpu-mcs", type=int, default=1000)
+    ap.add_argument("--t-max", type=int, default=T_MAX)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(replicas would shard with no communication; see the design notes)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1012_0385_amd as A
+
+    torch.cuda.set_device(0)
+    times = A.sample_times(30, 1.05, args.t_max)
+    if times[-1] != args.t_max:
+        times.append(args.t_max)
+    streams = [torch.cuda.Stream() for _ in MODELS]
+    sims = [A.Simulation(A.make_params(L=L, samples=SAMPLES, p=p, q=q, seed=1, stream=sid),
+                         stream=st) for (name, p, q, sid), st in zip(MODELS, streams)]
+    attempts_per_step = sum(s.samples * s.L for s in sims) * args.t_max
+
+    def run_one(sim, out, k):
+        sim.reset()
+        out[k] = sim.run(times)
+
+    def step_plain():
+        out = [None] * len(sims)
+        for k, s in enumerate(sims):
+            run_one(s, out, k)
+        return out
+
+    def step_batched():
+        out = [None] * len(sims)
+        th = [threading.Thread(target=run_one, args=(s, out, k)) for k, s in enumerate(sims)]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+        return out
+
+    def timed(step, n):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n):
+            step()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    for _ in range(args.warmup):
+        step_batched()
+    # plain form
+    t_plain = timed(step_plain, args.steps)
+    # batched form, with kernel timing on
+    for s in sims:
+        s.profile(True)
+    t_batch = timed(step_batched, args.steps)
+    prof = [s.profile_read() for s in sims]
+    for s in sims:
+        s.profile(False)
+    print("plain %.3f s, batched %.3f s over %d steps" % (t_plain, t_batch, args.steps),
+          file=sys.stderr)
+
+    value = attempts_per_step * args.steps / t_batch
+    plain_value = attempts_per_step * args.steps / t_plain
+    launches = sum(p["launches"] for p in prof)
+    kernel_ms = sum(p["kernel_ms"] for p in prof)
+    slots = sum(p["attempts"] * alu_slots_per_attempt(s) for p, s in zip(prof, sims))
+    avg_ms = kernel_ms / launches
+    achieved = slots / launches / (avg_ms * 1e-3)
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12,
+                "unit": "TOP/s", "frac": achieved / PEAK_SLOTS, "traffic": None,
+                "kernel": "k_ring", "avg_launch_ms": avg_ms, "launches": launches}
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(times, args.cpu_rings, args.cpu_mcs)
+
+    line = {
+        "metric": "site-updates/s (1 GPU)",
+        "value": value,
+        "unit": "site-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_batch / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64 bit planes, u32 Philox",
+        "data": "synthetic: flat (1010...) start, Philox4x32-10 noise keyed by (seed=1, stream, sample)",
+        "config": {"workload": "LDS-resident rings: L=2^17, half filling, flat start, KPZ (p=1,q=0) "
+                               "and EW (p=q=0.5), 64 samples each, 10^5 MCS, W^2 at t=0 and "
+                               "ceil(30*1.05^i)",
+                   "rings": len(sims) * SAMPLES, "L": L, "t_max": args.t_max,
+                   "measurements": len(times), "parallelism": "1 GPU"},
+        "plain": {"value": plain_value, "ms_per_step": t_plain / args.steps * 1e3},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -162,6 +162,22 @@ int asep_current(asep_sim* s, int64_t* hops);
  * checkpoint.  hops may be NULL (zeros). */
 int asep_set_time(asep_sim* s, uint64_t t, const int64_t* hops);
 
+/* Re-run the initialisation (state, quenched planes), set the clock and the
+ * hop counters to zero; no allocation.  Asynchronous on the stream. */
+int asep_reset(asep_sim* s);
+
+/* Kernel timing of the sweep launches (HIP events on the simulation's
+ * stream, taken only while enabled).  asep_profile_read synchronises and
+ * returns the number of sweep launches, their summed duration in ms and the
+ * elementary attempts they performed since enabling. */
+typedef struct asep_profile_stats {
+    uint64_t launches;
+    double kernel_ms;
+    uint64_t attempts;
+} asep_profile_stats;
+int asep_profile_enable(asep_sim* s, int enable);
+int asep_profile_read(asep_sim* s, asep_profile_stats* out);
+
 /* MCS completed so far (0 for a NULL handle). */
 uint64_t asep_time(const asep_sim* s);
 

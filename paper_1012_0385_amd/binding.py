@@ -66,6 +66,14 @@ class asep_rough(ctypes.Structure):
     ]
 
 
+class asep_profile_stats(ctypes.Structure):
+    _fields_ = [
+        ("launches", ctypes.c_uint64),
+        ("kernel_ms", ctypes.c_double),
+        ("attempts", ctypes.c_uint64),
+    ]
+
+
 class asep_server_cfg(ctypes.Structure):
     _fields_ = [
         ("abi_version", ctypes.c_uint32),
@@ -123,6 +131,9 @@ SIGNATURES = {
     "asep_read_mask": (_i32, [_vp, _u32, _u32, _P(_u64), _u64]),
     "asep_current": (_i32, [_vp, _P(ctypes.c_int64)]),
     "asep_set_time": (_i32, [_vp, _u64, _P(ctypes.c_int64)]),
+    "asep_reset": (_i32, [_vp]),
+    "asep_profile_enable": (_i32, [_vp, _i32]),
+    "asep_profile_read": (_i32, [_vp, _P(asep_profile_stats)]),
     "asep_time": (_u64, [_vp]),
     "asep_destroy": (None, [_vp]),
     "asep_ensemble_w2": (_i32, [_P(asep_rough), _u32, _u64, _P(ctypes.c_double)]),

@@ -226,7 +226,29 @@ struct asep_sim {
     void* own_aux = nullptr;
     uint64_t t = 0;
     std::vector<Record> host_rec;
+    // sweep-launch timing
+    bool prof = false;
+    std::vector<hipEvent_t> ev;     // pairs (start, stop)
+    std::vector<uint64_t> ev_att;   // attempts of each pending pair
+    size_t ev_pending = 0;
+    asep_profile_stats prof_acc{};
 };
+
+static const size_t kEvPairs = 64;
+
+// Add the durations of every recorded (start, stop) pair (waits for them).
+static int harvest_events(asep_sim* s) {
+    for (size_t i = 0; i < s->ev_pending; ++i) {
+        HIP_OR_FAIL(hipEventSynchronize(s->ev[2 * i + 1]));
+        float ms = 0.f;
+        HIP_OR_FAIL(hipEventElapsedTime(&ms, s->ev[2 * i], s->ev[2 * i + 1]));
+        s->prof_acc.launches += 1;
+        s->prof_acc.kernel_ms += ms;
+        s->prof_acc.attempts += s->ev_att[i];
+    }
+    s->ev_pending = 0;
+    return ASEP_OK;
+}
 
 static const uint32_t kRecCap = 64;  // measurement times per launch
 
@@ -340,6 +362,7 @@ extern "C" int asep_get_params(const asep_sim* s, asep_params* out) {
 extern "C" void asep_destroy(asep_sim* s) {
     if (!s) return;
     if (s->stream) (void)hipStreamSynchronize(s->stream);
+    for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
     if (s->own_state) (void)hipFree(s->own_state);
     if (s->own_aux) (void)hipFree(s->own_aux);
     if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
@@ -370,9 +393,54 @@ static int ring_launch(asep_sim* s, uint64_t t1, const uint64_t* rec_t_dev, uint
     a.spd = r.spd;
     a.real0 = r.real0;
     a.sc = r.sc;
+    const bool prof = s->prof;
+    if (prof) {
+        if (s->ev_pending == kEvPairs) {
+            int rc = harvest_events(s);
+            if (rc) return rc;
+        }
+        HIP_OR_FAIL(hipEventRecord(s->ev[2 * s->ev_pending], s->stream));
+    }
     HIP_OR_FAIL(launch_ring(a, s->shape.C, r.model, s->shape.block, s->shape.grid, s->shape.lds,
                             s->stream));
+    if (prof) {
+        HIP_OR_FAIL(hipEventRecord(s->ev[2 * s->ev_pending + 1], s->stream));
+        s->ev_att[s->ev_pending] = (t1 - s->t) * (uint64_t)r.P.samples * r.P.L * (r.planes == 2 ? 4 : 1);
+        s->ev_pending += 1;
+    }
     s->t = t1;
+    return ASEP_OK;
+}
+
+extern "C" int asep_profile_enable(asep_sim* s, int enable) {
+    if (!s) return ASEP_E_INVAL;
+    if (enable && s->ev.empty()) {
+        s->ev.resize(2 * kEvPairs);
+        s->ev_att.resize(kEvPairs);
+        for (auto& e : s->ev) HIP_OR_FAIL(hipEventCreate(&e));
+    }
+    if (!enable) {
+        int rc = harvest_events(s);
+        if (rc) return rc;
+    }
+    s->prof = enable != 0;
+    s->prof_acc = asep_profile_stats{};
+    return ASEP_OK;
+}
+
+extern "C" int asep_profile_read(asep_sim* s, asep_profile_stats* out) {
+    if (!s || !out) return ASEP_E_INVAL;
+    int rc = harvest_events(s);
+    if (rc) return rc;
+    *out = s->prof_acc;
+    return ASEP_OK;
+}
+
+extern "C" int asep_reset(asep_sim* s) {
+    if (!s) return ASEP_E_INVAL;
+    int rc = sim_init(s);
+    if (rc) return rc;
+    s->t = 0;
     return ASEP_OK;
 }
 

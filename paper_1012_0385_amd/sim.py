@@ -66,7 +66,8 @@ def _rough_arrays(arr, n: int) -> Rough:
 class Simulation:
     """An ensemble of rings on the GPU (asep_create_ext with torch buffers)."""
 
-    def __init__(self, params: B.asep_params, *, buffers: str = "torch", device: int = 0):
+    def __init__(self, params: B.asep_params, *, buffers: str = "torch", device: int = 0,
+                 stream=None):
         lib = B.load()
         self.params_in = params
         self._h = ctypes.c_void_p()
@@ -80,7 +81,7 @@ class Simulation:
             dev = torch.device("cuda", device)
             self.state_buf = torch.empty(max(sb.value, 8), dtype=torch.uint8, device=dev)
             self.aux_buf = torch.empty(max(ab.value, 8), dtype=torch.uint8, device=dev)
-            self.torch_stream = torch.cuda.current_stream(dev)
+            self.torch_stream = stream if stream is not None else torch.cuda.current_stream(dev)
             B.check(lib.asep_create_ext(ctypes.byref(params), self.state_buf.data_ptr(), sb.value,
                                         self.aux_buf.data_ptr(), ab.value,
                                         self.torch_stream.cuda_stream, ctypes.byref(self._h)),
@@ -158,6 +159,18 @@ class Simulation:
             h = np.ascontiguousarray(hops, dtype=np.int64)
             ptr = h.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
         B.check(B.load().asep_set_time(self._h, int(t), ptr), "asep_set_time")
+
+    def reset(self) -> None:
+        B.check(B.load().asep_reset(self._h), "asep_reset")
+
+    def profile(self, enable: bool = True) -> None:
+        B.check(B.load().asep_profile_enable(self._h, 1 if enable else 0), "asep_profile_enable")
+
+    def profile_read(self) -> dict:
+        st = B.asep_profile_stats()
+        B.check(B.load().asep_profile_read(self._h, ctypes.byref(st)), "asep_profile_read")
+        return {"launches": int(st.launches), "kernel_ms": float(st.kernel_ms),
+                "attempts": int(st.attempts)}
 
     def close(self) -> None:
         if self._h:
