@@ -8,8 +8,9 @@ Eq. (sampling) (t_0 = 30, factor 1.05: 168 measurements).  One step = one
 such job: reset of both ensembles (init kernels) and their full runs.
 
 Two forms are timed: "plain" runs the two ensembles one after the other
-(one run per launch sequence); "batched" runs them concurrently on two
-streams.  value = elementary update attempts (site updates) per second of
+(one run per launch sequence); "batched" advances both through
+asep_run_batch (each on its own stream, all launches queued before any
+wait).  value = elementary update attempts (site updates) per second of
 the batched form.
 
 The JSON line also carries the ALU roofline of the dominant kernel (the
@@ -21,7 +22,6 @@ import argparse
 import json
 import os
 import sys
-import threading
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -112,13 +112,9 @@ def main():
         return out
 
     def step_batched():
-        out = [None] * len(sims)
-        th = [threading.Thread(target=run_one, args=(s, out, k)) for k, s in enumerate(sims)]
-        for t in th:
-            t.start()
-        for t in th:
-            t.join()
-        return out
+        for s in sims:
+            s.reset()
+        return A.run_batch(sims, times)
 
     def timed(step, n):
         torch.cuda.synchronize()
@@ -151,7 +147,7 @@ def main():
     achieved = slots / launches / (avg_ms * 1e-3)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12,
                 "unit": "TOP/s", "frac": achieved / PEAK_SLOTS, "traffic": None,
-                "kernel": "k_ring", "avg_launch_ms": avg_ms, "launches": launches}
+                "kernel": "k_sweep", "avg_launch_ms": avg_ms, "launches": launches}
 
     cpu = None
     if not args.no_cpu:

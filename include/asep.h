@@ -90,7 +90,11 @@ typedef struct asep_params {
     int32_t rbits;     /* bits compared against each acceptance threshold:
                           -1 = the fewest that keep every threshold exact,
                           else an explicit count (ASEP_E_INVAL if inexact) */
-    uint32_t reserved[3];
+    uint32_t windows;  /* launch shape only, never results: 0 = automatic,
+                          1 = each ring whole in one workgroup, n >= 2 = each
+                          ring cut into n windows (one workgroup each) */
+    uint32_t window_sweeps; /* sub-sweeps per launch of a windowed ring; 0 = 63 */
+    uint32_t reserved;
 } asep_params;
 
 /* Roughness and current of one sample at one time (Sec. 2.1, Eq. W).
@@ -144,6 +148,15 @@ int asep_roughness(asep_sim* s, asep_rough* out);
  * measure at each: out[n_times * samples] (host array, time-major).  Equal to
  * asep_sweep + asep_roughness at each time, bit for bit.  Synchronises. */
 int asep_run(asep_sim* s, const uint64_t* times, uint32_t n_times, asep_rough* out);
+
+/* asep_run for several simulations at once: every simulation advances
+ * through the same times, each on its own stream, their launches queued
+ * before the call waits on any of them so that they overlap on the GPU.
+ * outs[k] receives simulation k's n_times x samples records.  Each result
+ * equals that simulation's asep_run alone.  The simulations must be distinct
+ * and all at or before times[0]. */
+int asep_run_batch(asep_sim* const* sims, uint32_t n_sims, const uint64_t* times,
+                   uint32_t n_times, asep_rough* const* outs);
 
 /* Copy one sample's state words (planes x L/64 uint64, lane A first) to or
  * from host memory; n_words must equal planes x L/64.  Synchronises. */

@@ -51,7 +51,9 @@ class asep_params(ctypes.Structure):
         ("cell_log2", ctypes.c_int32),
         ("subsweeps", ctypes.c_int32),
         ("rbits", ctypes.c_int32),
-        ("reserved", ctypes.c_uint32 * 3),
+        ("windows", ctypes.c_uint32),
+        ("window_sweeps", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
     ]
 
 
@@ -126,6 +128,7 @@ SIGNATURES = {
     "asep_sweep": (_i32, [_vp, _u64]),
     "asep_roughness": (_i32, [_vp, _P(asep_rough)]),
     "asep_run": (_i32, [_vp, _P(_u64), _u32, _P(asep_rough)]),
+    "asep_run_batch": (_i32, [_P(_vp), _u32, _P(_u64), _u32, _P(_P(asep_rough))]),
     "asep_read_state": (_i32, [_vp, _u32, _P(_u64), _u64]),
     "asep_write_state": (_i32, [_vp, _u32, _P(_u64), _u64]),
     "asep_read_mask": (_i32, [_vp, _u32, _u32, _P(_u64), _u64]),

@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libasep.so")
-SOURCES = ["asep_kernels.hip", "asep_host.cpp", "asep_server.cpp"]
+SOURCES = ["asep_kernels.hip", "asep_sweep_plain.hip", "asep_sweep_disorder.hip",
+           "asep_sweep_two_lane.hip", "asep_host.cpp", "asep_server.cpp"]
 ARCH = "gfx950"
 
 

@@ -1,0 +1,762 @@
+// asep_device.h -- device code shared by the gfx950 kernel translation units:
+// Philox4x32-10, bit helpers, height-moment tables, the per-cell attempt
+// loops and the sweep kernel template.  Included only by .hip files.
+//
+// Random numbers: Philox4x32-10 (Salmon et al., SC'11) keyed by (seed,
+// stream); counters
+//   attempt: (cell k, lo32(g), 1<<28 | blk<<16 | hi16(g), sample)
+//   shift:   (0, lo32(g/4), 2<<28 | hi16(g/4), sample), word g mod 4
+//   init:    (site/4, lane, 3<<28, sample), word site mod 4
+//   masks:   (site/4, 0, tag<<28, realisation), word site mod 4
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "asep_internal.h"
+
+namespace asep {
+namespace dev {
+
+constexpr uint32_t kMulA = 0xD2511F53u;
+constexpr uint32_t kMulB = 0xCD9E8D57u;
+constexpr uint32_t kWeylA = 0x9E3779B9u;
+constexpr uint32_t kWeylB = 0xBB67AE85u;
+
+struct Blk {
+    uint32_t v[4];
+};
+
+// Ten Philox rounds: products of counter words 0 and 2, high halves mixed
+// with the other two words and the round key, Weyl key schedule.
+__device__ __forceinline__ Blk philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                      uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int i = 0; i < 10; ++i) {
+        const uint64_t pa = (uint64_t)kMulA * (uint64_t)c0;
+        const uint64_t pb = (uint64_t)kMulB * (uint64_t)c2;
+        const uint32_t n0 = (uint32_t)(pb >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(pa >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)pb;
+        c3 = (uint32_t)pa;
+        c0 = n0;
+        c2 = n2;
+        k0 += kWeylA;
+        k1 += kWeylB;
+    }
+    Blk b;
+    b.v[0] = c0;
+    b.v[1] = c1;
+    b.v[2] = c2;
+    b.v[3] = c3;
+    return b;
+}
+
+// 64 sites starting `sh` bits into `lo`, continuing into `hi`; sh in [0, 63].
+__device__ __forceinline__ uint64_t funnel(uint64_t lo, uint64_t hi, uint32_t sh) {
+    return (lo >> sh) | ((hi << 1) << (63u - sh));
+}
+
+__device__ __forceinline__ uint32_t bfe(uint32_t v, uint32_t off, uint32_t width) {
+    return __builtin_amdgcn_ubfe(v, off, width);
+}
+
+// Sums of heights inside one word relative to the height at its first site:
+// E1 = sum_q d_q, E2 = sum_q d_q^2 with d_0 = 0, d_{q+1} = d_q + 1 - 2 n_q
+// (Eq. W's h restricted to one word); tab1/tab2 hold the same sums per byte.
+__device__ __forceinline__ void word_moments(uint64_t word, const int32_t* tab1,
+                                             const int32_t* tab2, int64_t& e1, int64_t& e2) {
+    int64_t d = 0;
+    e1 = 0;
+    e2 = 0;
+#pragma unroll
+    for (int by = 0; by < 8; ++by) {
+        const uint32_t byte = (uint32_t)(word >> (8 * by)) & 255u;
+        const int64_t t1 = tab1[byte];
+        e1 += 8 * d + t1;
+        e2 += 8 * d * d + 2 * d * t1 + tab2[byte];
+        d += 8 - 2 * (int64_t)__popc(byte);
+    }
+}
+
+__device__ inline void build_byte_tables(int32_t* tab1, int32_t* tab2) {
+    for (uint32_t v = threadIdx.x; v < 256; v += blockDim.x) {
+        int32_t e = 0, s = 0, s2 = 0;
+        for (int q = 0; q < 8; ++q) {
+            s += e;
+            s2 += e * e;
+            e += 1 - 2 * (int32_t)((v >> q) & 1u);
+        }
+        tab1[v] = s;
+        tab2[v] = s2;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Attempt loops.  One call runs the `na` attempts of one cell in one
+// sub-sweep (Sec. 2.1's exchange rules under the shifted decomposition):
+// attempt m takes field (m mod A) of word ((m / A) mod 4) of Philox block
+// m / 4A; a field is [j | e | r] from the top (e only for two lanes).
+// ---------------------------------------------------------------------------
+struct CellCtx {
+    uint32_t k;       // cell index
+    uint32_t glo;     // lo32(g)
+    uint32_t c2b;     // attempt tag | hi16(g)
+    uint32_t sample;
+    uint32_t k0, k1;  // key
+    uint32_t na, nblk, b, w, A;
+    uint32_t T0, T1, T2, T3;
+    uint32_t lut;     // packed 8-bit thresholds {0, T0, T1, 0} for pair 0..3
+    uint32_t lut3;    // packed flips {0, 3 T0, 3 T1, 0} (thresholds of 0 bits)
+};
+
+// Generic single-lane cell: any cell size ell <= 64 located at bit `bb` of
+// the slot; the attempt count per word is a runtime value.
+template <bool DIS>
+__device__ __forceinline__ int32_t cell_ring_generic(uint64_t& x, uint64_t m0, uint64_t m1,
+                                                      uint32_t bb, uint32_t lam,
+                                                      const CellCtx& c) {
+    const uint32_t cmask = (1u << lam) - 1u;
+    const uint32_t rmask = (c.b >= 32) ? 0xFFFFFFFFu : ((1u << c.b) - 1u);
+    int32_t dj = 0;
+    uint32_t m = 0;
+    for (uint32_t blk = 0; blk < c.nblk; ++blk) {
+        const Blk r = philox(c.k, c.glo, c.c2b | (blk << 16), c.sample, c.k0, c.k1);
+#pragma unroll
+        for (int wd = 0; wd < 4; ++wd) {
+            const uint32_t u = r.v[wd];
+            for (uint32_t sl = 0; sl < c.A && m < c.na; ++sl, ++m) {
+                const uint32_t sh = sl * c.w;
+                const uint32_t rv = (u >> sh) & rmask;
+                const uint32_t j = (u >> (sh + c.b)) & cmask;
+                const uint32_t pos = bb + j;
+                const uint32_t pr = (uint32_t)(x >> pos) & 3u;
+                uint32_t tp = c.T0, tq = c.T1;
+                if (DIS) {
+                    if ((m0 >> pos) & 1u) tp = c.T2;
+                    if (((m1 >> pos) >> 1) & 1u) tq = c.T3;
+                }
+                const bool live = j != cmask;
+                const bool fwd = live && pr == 1u && rv < tp;
+                const bool bwd = live && pr == 2u && rv < tq;
+                x ^= (uint64_t)((fwd || bwd) ? 3u : 0u) << pos;
+                dj += (int32_t)fwd - (int32_t)bwd;
+            }
+        }
+    }
+    return dj;
+}
+
+// Single lane, ell = 64 (one cell per slot), default schedule: NA attempts
+// per cell per sub-sweep, A fields per 32-bit word and BB compared bits known
+// at compile time (BB < 0: runtime).  The pair (x, x+1) is read with an
+// arithmetic shift: at j = 63 the top bit is replicated, the pair is 00 or
+// 11 and nothing can hop, which is exactly the no-op of the bond leaving the
+// cell.  With BB = 0 the acceptance is decided by the pair alone, so one
+// packed table gives the flip pattern (0 or 3) directly.  Q0: no backward
+// hops (q = 0): every flip is a right hop.
+template <int A, int BB, bool Q0, bool DIS, int NA>
+__device__ __forceinline__ int32_t cell_ring_fast(uint64_t& x, uint64_t m0, uint64_t m1,
+                                                   const CellCtx& c) {
+    constexpr int PER = 4 * A;
+    constexpr int NB = (NA + PER - 1) / PER;
+    int32_t dj = 0;
+#pragma unroll
+    for (int blk = 0; blk < NB; ++blk) {
+        const Blk r = philox(c.k, c.glo, c.c2b | ((uint32_t)blk << 16), c.sample, c.k0, c.k1);
+#pragma unroll
+        for (int wd = 0; wd < 4; ++wd) {
+#pragma unroll
+            for (int sl = 0; sl < A; ++sl) {
+                if (blk * PER + wd * A + sl >= NA) continue;
+                const uint32_t u = r.v[wd];
+                const uint32_t b = BB >= 0 ? (uint32_t)BB : c.b;
+                const uint32_t sh = BB >= 0 ? (uint32_t)(sl * (6 + BB)) : (uint32_t)sl * c.w;
+                const uint32_t j = bfe(u, sh + b, 6);
+                const int64_t sx = (int64_t)x >> j;
+                const uint32_t pr = (uint32_t)sx & 3u;
+                uint32_t f;
+                if (BB == 0 && !DIS) {
+                    // the field offset of v_bfe_u32 is taken mod 32: (sx << 3) mod 32 = 8 pr
+                    f = bfe(c.lut3, (uint32_t)sx << 3, 8);
+                } else {
+                    const uint32_t rv = (BB == 0) ? 0u : bfe(u, sh, b);
+                    uint32_t tsel;
+                    if (DIS) {
+                        const uint32_t tp = ((m0 >> j) & 1u) ? c.T2 : c.T0;
+                        uint32_t tq = 0;
+                        if (!Q0) tq = (((m1 >> j) >> 1) & 1u) ? c.T3 : c.T1;
+                        tsel = pr == 1u ? tp : (pr == 2u ? tq : 0u);
+                    } else if (BB >= 0 && BB <= 7) {
+                        tsel = bfe(c.lut, (uint32_t)sx << 3, 8);
+                    } else {
+                        tsel = pr == 1u ? c.T0 : (pr == 2u ? c.T1 : 0u);
+                    }
+                    f = (rv < tsel) ? 3u : 0u;
+                }
+                x ^= (uint64_t)f << j;
+                if (Q0)
+                    dj += (int32_t)f;  // 3 per right hop
+                else
+                    dj += f ? (int32_t)(3u - 2u * pr) : 0;
+            }
+        }
+    }
+    return Q0 ? dj / 3 : dj;
+}
+
+// Two lanes (Sec. 3): events 0 = A hops right on (x, x+1), 1 = B hops left
+// from x+1 to x, 2 = A->B at x, 3 = B->A at x (turning point, other lane
+// empty).  Bond events at j = ell-1 are no-ops; site events use every j.
+__device__ __forceinline__ void two_lane_event(uint64_t& xa, uint64_t& xb, uint32_t pa,
+                                               uint32_t pb, uint32_t tt, uint32_t e, uint32_t rv,
+                                               bool live, uint32_t pos, const CellCtx& c,
+                                               int32_t& dj) {
+    const bool hopA = e == 0u && live && pa == 1u && rv < c.T0;
+    const bool hopB = e == 1u && live && pb == 2u && rv < c.T1;
+    const uint32_t a0 = pa & 1u, b0 = pb & 1u;
+    const bool chg = e >= 2u && tt && a0 != b0 && a0 == (e == 2u ? 1u : 0u) && rv < c.T2;
+    const uint32_t ch = chg ? 1u : 0u;
+    xa ^= (uint64_t)(hopA ? 3u : ch) << pos;
+    xb ^= (uint64_t)(hopB ? 3u : ch) << pos;
+    dj += (int32_t)hopA - (int32_t)hopB;
+}
+
+// Any cell size ell <= 64 at bit `bb` of the slot, runtime fields per word.
+__device__ __forceinline__ int32_t cell_two_lane_generic(uint64_t& xa, uint64_t& xb, uint64_t tm,
+                                                          uint32_t bb, uint32_t lam,
+                                                          const CellCtx& c) {
+    const uint32_t cmask = (1u << lam) - 1u;
+    const uint32_t rmask = (c.b >= 32) ? 0xFFFFFFFFu : ((1u << c.b) - 1u);
+    int32_t dj = 0;
+    uint32_t m = 0;
+    for (uint32_t blk = 0; blk < c.nblk; ++blk) {
+        const Blk r = philox(c.k, c.glo, c.c2b | (blk << 16), c.sample, c.k0, c.k1);
+#pragma unroll
+        for (int wd = 0; wd < 4; ++wd) {
+            const uint32_t u = r.v[wd];
+            for (uint32_t sl = 0; sl < c.A && m < c.na; ++sl, ++m) {
+                const uint32_t sh = sl * c.w;
+                const uint32_t rv = (u >> sh) & rmask;
+                const uint32_t e = (u >> (sh + c.b)) & 3u;
+                const uint32_t j = (u >> (sh + c.b + 2)) & cmask;
+                const uint32_t pos = bb + j;
+                const uint32_t pa = (uint32_t)(xa >> pos) & 3u;
+                const uint32_t pb = (uint32_t)(xb >> pos) & 3u;
+                const uint32_t tt = (uint32_t)(tm >> pos) & 1u;
+                two_lane_event(xa, xb, pa, pb, tt, e, rv, j != cmask, pos, c, dj);
+            }
+        }
+    }
+    return dj;
+}
+
+// ell = 64, default schedule (NA attempts per cell per sub-sweep), A fields
+// per word and BB compared bits known at compile time (BB < 0: runtime); the
+// arithmetic-shift pair read makes bond events at j = 63 no-ops while site
+// events there stay live.
+template <int A, int BB, int NA>
+__device__ __forceinline__ int32_t cell_two_lane_fast(uint64_t& xa, uint64_t& xb, uint64_t tm,
+                                                       const CellCtx& c) {
+    constexpr int PER = 4 * A;
+    constexpr int NB = (NA + PER - 1) / PER;
+    int32_t dj = 0;
+#pragma unroll
+    for (int blk = 0; blk < NB; ++blk) {
+        const Blk r = philox(c.k, c.glo, c.c2b | ((uint32_t)blk << 16), c.sample, c.k0, c.k1);
+#pragma unroll
+        for (int wd = 0; wd < 4; ++wd) {
+#pragma unroll
+            for (int sl = 0; sl < A; ++sl) {
+                if (blk * PER + wd * A + sl >= NA) continue;
+                const uint32_t u = r.v[wd];
+                const uint32_t b = BB >= 0 ? (uint32_t)BB : c.b;
+                const uint32_t sh = BB >= 0 ? (uint32_t)(sl * (8 + BB)) : (uint32_t)sl * c.w;
+                const uint32_t rv = (BB == 0) ? 0u : bfe(u, sh, b);
+                const uint32_t e = bfe(u, sh + b, 2);
+                const uint32_t j = bfe(u, sh + b + 2, 6);
+                const uint32_t pa = (uint32_t)((int64_t)xa >> j) & 3u;
+                const uint32_t pb = (uint32_t)((int64_t)xb >> j) & 3u;
+                const uint32_t tt = (uint32_t)(tm >> j) & 1u;
+                two_lane_event(xa, xb, pa, pb, tt, e, rv, true, j, c, dj);
+            }
+        }
+    }
+    return dj;
+}
+
+// Variants of the attempt loop.  The fast ones need ell = 64 and the default
+// four sub-sweeps per MCS (16 attempts per cell and sub-sweep on one lane,
+// 64 on two lanes).
+enum Variant : int {
+    kGeneric = 0,
+    kF5B0 = 1,  // 5 fields per word, no threshold bits (p, q in {0, 1})
+    kF4B1 = 2,  // 4 fields per word, 1 threshold bit (e.g. p = q = 1/2)
+    kF4B2 = 3,  // 4 fields per word, 2 threshold bits
+    kF1 = 4,    // 1 field per word, threshold bits at run time
+    kF4B0 = 5,  // two lanes: 4 fields per word, no threshold bits
+};
+
+template <int V>
+struct VarInfo {
+    static constexpr int A = 0, BB = -1;
+};
+template <>
+struct VarInfo<kF5B0> {
+    static constexpr int A = 5, BB = 0;
+};
+template <>
+struct VarInfo<kF4B1> {
+    static constexpr int A = 4, BB = 1;
+};
+template <>
+struct VarInfo<kF4B2> {
+    static constexpr int A = 4, BB = 2;
+};
+template <>
+struct VarInfo<kF1> {
+    static constexpr int A = 1, BB = -1;
+};
+template <>
+struct VarInfo<kF4B0> {
+    static constexpr int A = 4, BB = 0;
+};
+
+// Dynamic LDS of the sweep kernel, in this order:
+//   xch   [2][block][planes] uint64  neighbour exchange, double-buffered
+//   mask  [rings_per_wg][mplanes][mwords] uint64
+//   red   [rings_per_wg][4] uint64     per-ring reductions
+//   scan  [2][block] int32
+//   tab   [2][256] int32
+//   g0    [rings_per_wg] int32
+__host__ __device__ inline size_t sweep_lds_layout(uint32_t block, uint32_t planes, uint32_t G,
+                                                   uint32_t mplanes, uint32_t mwords,
+                                                   size_t* o_mask, size_t* o_red, size_t* o_scan,
+                                                   size_t* o_tab, size_t* o_g0) {
+    size_t off = (size_t)2 * block * planes * 8;
+    *o_mask = off;
+    off += (size_t)G * mplanes * mwords * 8;
+    *o_red = off;
+    off += (size_t)G * 4 * 8;
+    *o_scan = off;
+    off += (size_t)2 * block * 4;
+    *o_tab = off;
+    off += 2 * 256 * 4;
+    *o_g0 = off;
+    off += (size_t)G * 4;
+    return (off + 15) & ~(size_t)15;
+}
+
+// Largest workgroup for C slots per lane: more slots need more VGPRs
+// (gfx950: 512 VGPRs per SIMD lane; a 512-lane workgroup is 2 waves per SIMD).
+__host__ __device__ constexpr uint32_t sweep_max_block(int C, int model = kPlain) {
+    return (C == 1 || (C == 2 && model != kTwoLane)) ? 1024u : 512u;
+}
+
+// ---------------------------------------------------------------------------
+// The sweep kernel.  A workgroup serves either G whole rings (segs == 1:
+// the ring is periodic, measurements may be taken inside the launch) or one
+// window of one ring (segs > 1): output words [s0, s0+n) plus `halo` words
+// on each side, advanced by at most halo-1 sub-sweeps; garbage enters the
+// window from its right end one slot per sub-sweep and the window drifts
+// right by at most one slot per sub-sweep, so the output words are exact.
+// Lane lt owns window slots [lt*C, lt*C+C); slot i holds the 64 sites
+// starting at sig + 64*(base + off + i) (mod L).
+// ---------------------------------------------------------------------------
+template <int C, int MODEL, int V, bool Q0>
+__global__ __launch_bounds__(sweep_max_block(C, MODEL)) void k_sweep(const SimDesc P) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int NPL = (MODEL == kTwoLane) ? 2 : 1;
+    constexpr bool FAST = V != kGeneric;
+    constexpr int AV = VarInfo<V>::A;
+    constexpr int BV = VarInfo<V>::BB;
+
+    const uint32_t lb = blockIdx.x - P.wg_begin;
+
+    const uint32_t tid = threadIdx.x;
+    const uint32_t block = blockDim.x;
+    const uint32_t Tr = P.lanes_per_ring;
+    const uint32_t G = P.rings_per_wg;
+    const bool seg = P.segs > 1;
+    const uint32_t gi = tid / Tr;
+    const uint32_t lt = tid - gi * Tr;
+    const uint32_t ring = seg ? lb / P.segs : lb * G + gi;
+    const uint32_t sidx = seg ? lb % P.segs : 0;
+    const bool ring_ok = (gi < G) && (ring < P.R);
+    const uint32_t nw = P.nw;
+    const uint32_t nslot = seg ? P.nslot : nw;
+    const uint32_t nact = (nslot + C - 1) / C;
+    const bool act = ring_ok && lt < nact;
+    const uint32_t base_slot = lt * C;
+    const int cnt = act ? (int)min((uint32_t)C, nslot - base_slot) : 0;
+    const uint32_t sample = P.sample0 + (ring_ok ? ring : 0);
+    const uint32_t lane0 = gi * Tr;
+    const uint32_t nxt = lane0 + ((lt + 1 < nact) ? lt + 1 : 0);
+    // window origin (whole ring: 0) and the output range in window positions
+    const uint32_t s0 = sidx * P.seg_n;
+    const uint32_t nout = seg ? min(P.seg_n, nw - s0) : nw;
+    const uint32_t halo = seg ? P.halo : 0;
+    const uint32_t base = seg ? (s0 + nw - halo) % nw : 0;
+    const uint32_t mwords = seg ? nslot + halo + 2 : nw;
+
+    size_t o_mask, o_red, o_scan, o_tab, o_g0;
+    sweep_lds_layout(block, NPL, G, P.mplanes, mwords, &o_mask, &o_red, &o_scan, &o_tab, &o_g0);
+    uint64_t* xch = reinterpret_cast<uint64_t*>(smem);
+    uint64_t* lmask = reinterpret_cast<uint64_t*>(smem + o_mask) +
+                      (size_t)(gi < G ? gi : 0) * P.mplanes * mwords;
+    unsigned long long* red = reinterpret_cast<unsigned long long*>(smem + o_red);
+    int32_t* scan = reinterpret_cast<int32_t*>(smem + o_scan);
+    int32_t* tab1 = reinterpret_cast<int32_t*>(smem + o_tab);
+    int32_t* tab2 = tab1 + 256;
+    int32_t* g0s = reinterpret_cast<int32_t*>(smem + o_g0);
+
+    const uint32_t lam = P.sc.lam;
+    const uint32_t cmask = (1u << lam) - 1u;
+    const uint32_t cps = 64u >> lam;
+
+    CellCtx cc;
+    cc.sample = sample;
+    cc.k0 = P.key0;
+    cc.k1 = P.key1;
+    cc.na = P.sc.a;
+    cc.nblk = P.sc.nblk;
+    cc.b = P.sc.b;
+    cc.w = P.sc.w;
+    cc.A = P.sc.A;
+    cc.T0 = P.sc.T[0];
+    cc.T1 = P.sc.T[1];
+    cc.T2 = P.sc.T[2];
+    cc.T3 = P.sc.T[3];
+    cc.lut = (P.sc.T[0] << 8) | (P.sc.T[1] << 16);
+    cc.lut3 = ((3u * P.sc.T[0]) << 8) | ((3u * P.sc.T[1]) << 16);
+
+    // load the window (whole ring: every word)
+    uint64_t sa[C];
+    uint64_t sb[C];
+#pragma unroll
+    for (int i = 0; i < C; ++i) {
+        sa[i] = 0;
+        sb[i] = 0;
+        if (i < cnt) {
+            uint32_t w = base + base_slot + (uint32_t)i;
+            if (w >= nw) w -= nw;
+            const uint64_t* src = P.words_in + (size_t)ring * NPL * nw;
+            sa[i] = src[w];
+            if (MODEL == kTwoLane) sb[i] = src[nw + w];
+        }
+    }
+    if (MODEL != kPlain && ring_ok) {
+        const uint32_t real = sample / P.spd - P.real0;
+        const uint64_t* msrc = P.masks + (size_t)real * P.mplanes * nw;
+        for (uint32_t pl = 0; pl < P.mplanes; ++pl)
+            for (uint32_t idx = lt; idx < mwords; idx += Tr) {
+                uint32_t w = base + idx;
+                while (w >= nw) w -= nw;
+                lmask[pl * mwords + idx] = msrc[(size_t)pl * nw + w];
+            }
+    }
+    if (P.n_rec) build_byte_tables(tab1, tab2);
+    __syncthreads();
+
+    uint32_t sig = 0, off = 0, buf = 0;
+    int64_t J = 0;
+    const int64_t hops0 = (ring_ok && !seg) ? P.hops[ring] : 0;
+
+    // Move every slot to the shift sig_new (neighbour exchange through LDS).
+    auto shift_to = [&](uint32_t sig_new) {
+        const uint32_t delta = (sig_new - sig) & 63u;
+        const bool wrap = sig_new < sig;
+        uint64_t* xb = xch + (size_t)buf * block * NPL;
+        if (act) {
+            xb[tid * NPL] = sa[0];
+            if (MODEL == kTwoLane) xb[tid * NPL + 1] = sb[0];
+        }
+        __syncthreads();
+        if (act) {
+            const uint64_t na_ = xb[nxt * NPL];
+            const uint64_t nb_ = (MODEL == kTwoLane) ? xb[nxt * NPL + 1] : 0;
+#pragma unroll
+            for (int i = 0; i < C; ++i) {
+                if (i < cnt) {
+                    uint64_t ha = na_, hb = nb_;
+                    if (i + 1 < C && i + 1 < cnt) {
+                        ha = sa[i + 1 < C ? i + 1 : i];
+                        hb = sb[i + 1 < C ? i + 1 : i];
+                    }
+                    sa[i] = funnel(sa[i], ha, delta);
+                    if (MODEL == kTwoLane) sb[i] = funnel(sb[i], hb, delta);
+                }
+            }
+        }
+        if (wrap) {
+            off += 1;
+            if (!seg && off == nw) off = 0;
+        }
+        sig = sig_new;
+        buf ^= 1u;
+    };
+
+    // Heights and exact sums of a whole ring (slots at shift 0).
+    auto measure = [&](uint32_t ri) {
+        // slot base_slot+i holds word (off + base_slot + i) mod nw
+        int32_t dl = 0;
+#pragma unroll
+        for (int i = 0; i < C; ++i)
+            if (i < cnt) dl += 64 - 2 * (int32_t)__popcll(sa[i]);
+        int32_t* s0p = scan;
+        int32_t* s1p = scan + block;
+        s0p[tid] = dl;
+        if (lt == 0 && gi < G) {
+            red[gi * 4 + 0] = 0;
+            red[gi * 4 + 1] = 0;
+            red[gi * 4 + 2] = 0;
+            red[gi * 4 + 3] = 0;
+        }
+        __syncthreads();
+        for (uint32_t d = 1; d < block; d <<= 1) {
+            const int32_t v = s0p[tid] + (tid >= d ? s0p[tid - d] : 0);
+            __syncthreads();
+            s1p[tid] = v;
+            __syncthreads();
+            int32_t* t = s0p;
+            s0p = s1p;
+            s1p = t;
+        }
+        const int32_t before = (lane0 > 0) ? s0p[lane0 - 1] : 0;
+        const int32_t excl = s0p[tid] - dl - before;
+        const int32_t last = lane0 + Tr - 1 < block ? lane0 + Tr - 1 : block - 1;
+        const int32_t gtot = s0p[last] - before;
+        const uint32_t i0 = (nw - off) % nw;  // slot holding word 0
+        if (act && i0 >= base_slot && i0 < base_slot + (uint32_t)cnt) {
+            int32_t g = excl;
+#pragma unroll
+            for (int i = 0; i < C; ++i)
+                if ((uint32_t)i < i0 - base_slot) g += 64 - 2 * (int32_t)__popcll(sa[i]);
+            g0s[gi] = g;
+        }
+        __syncthreads();
+        int64_t ls1 = 0;
+        uint64_t ls2 = 0;
+        int64_t ln = 0;
+        if (act) {
+            const int32_t gz = g0s[gi];
+            int32_t g = excl;
+#pragma unroll
+            for (int i = 0; i < C; ++i) {
+                if (i < cnt) {
+                    const uint32_t idx = base_slot + i;
+                    const int64_t H = (idx >= i0) ? (int64_t)(g - gz) : (int64_t)(g + gtot - gz);
+                    int64_t e1, e2;
+                    word_moments(sa[i], tab1, tab2, e1, e2);
+                    ls1 += 64 * H + e1;
+                    ls2 += (uint64_t)(64 * H * H + 2 * H * e1 + e2);
+                    ln += __popcll(sa[i]);
+                    if (MODEL == kTwoLane) ln += __popcll(sb[i]);
+                    g += 64 - 2 * (int32_t)__popcll(sa[i]);
+                }
+            }
+        }
+        if (act) {
+            atomicAdd(&red[gi * 4 + 0], (unsigned long long)ls1);
+            atomicAdd(&red[gi * 4 + 1], (unsigned long long)ls2);
+            atomicAdd(&red[gi * 4 + 2], (unsigned long long)J);
+            atomicAdd(&red[gi * 4 + 3], (unsigned long long)ln);
+        }
+        __syncthreads();
+        if (ring_ok && lt == 0) {
+            Record rc;
+            rc.s1 = (int64_t)red[gi * 4 + 0];
+            rc.s2lo = (uint64_t)red[gi * 4 + 1];
+            rc.s2hi = 0;
+            rc.hops = hops0 + (int64_t)red[gi * 4 + 2];
+            rc.n = (int64_t)red[gi * 4 + 3];
+            P.rec[(size_t)ri * P.R + ring] = rc;
+        }
+        __syncthreads();
+    };
+
+    uint32_t shblk[4] = {0, 0, 0, 0};
+    uint64_t shq = ~0ull;
+    uint32_t ri = 0;
+    for (uint64_t g = P.g0;; ++g) {
+        while (ri < P.n_rec && P.rec_g[ri] == g) {
+            shift_to(0);  // uniform call: rings of one workgroup may differ in sig
+            measure(ri);
+            ++ri;
+        }
+        if (g >= P.g1) break;
+        const uint64_t quad = g >> 2;
+        if (quad != shq) {
+            const Blk r = philox(0u, (uint32_t)quad,
+                                 (kTagShift << 28) | (uint32_t)((quad >> 32) & 0xFFFFu), sample,
+                                 cc.k0, cc.k1);
+            shblk[0] = r.v[0];
+            shblk[1] = r.v[1];
+            shblk[2] = r.v[2];
+            shblk[3] = r.v[3];
+            shq = quad;
+        }
+        const uint32_t gq = (uint32_t)(g & 3u);
+        const uint32_t sw = gq == 0 ? shblk[0] : gq == 1 ? shblk[1] : gq == 2 ? shblk[2] : shblk[3];
+        shift_to(sw & cmask);
+
+        cc.glo = (uint32_t)g;
+        cc.c2b = (kTagAttempt << 28) | (uint32_t)((g >> 32) & 0xFFFFu);
+        // word of the window position of slot 0 of this lane
+        uint32_t wb = base + off + base_slot;
+        while (wb >= nw) wb -= nw;
+        int32_t dj = 0;
+#pragma unroll
+        for (int i = 0; i < C; ++i) {
+            if (i < cnt) {
+                uint32_t w = wb + (uint32_t)i;
+                if (w >= nw) w -= nw;
+                const uint32_t pos = off + base_slot + (uint32_t)i;  // window position
+                uint64_t xa = sa[i];
+                uint64_t xb = sb[i];
+                uint64_t m0 = 0, m1 = 0;
+                if (MODEL != kPlain) {
+                    uint32_t ia, ib;
+                    if (seg) {
+                        ia = min(pos, mwords - 2);
+                        ib = ia + 1;
+                    } else {
+                        ia = w;
+                        ib = (w + 1 == nw) ? 0 : w + 1;
+                    }
+                    m0 = funnel(lmask[ia], lmask[ib], sig);
+                    if (MODEL == kDisorder && P.mplanes > 1)
+                        m1 = funnel(lmask[mwords + ia], lmask[mwords + ib], sig);
+                }
+                int32_t d = 0;
+                if constexpr (FAST) {
+                    cc.k = w;
+                    if (MODEL == kTwoLane)
+                        d = cell_two_lane_fast<AV, BV, 64>(xa, xb, m0, cc);
+                    else
+                        d = cell_ring_fast<AV, BV, Q0, MODEL == kDisorder, 16>(xa, m0, m1, cc);
+                } else {
+                    for (uint32_t cq = 0; cq < cps; ++cq) {
+                        cc.k = w * cps + cq;
+                        const uint32_t bb = cq << lam;
+                        if (MODEL == kTwoLane)
+                            d += cell_two_lane_generic(xa, xb, m0, bb, lam, cc);
+                        else
+                            d += cell_ring_generic<MODEL == kDisorder>(xa, m0, m1, bb, lam, cc);
+                    }
+                }
+                sa[i] = xa;
+                if (MODEL == kTwoLane) sb[i] = xb;
+                // a window counts the hops of the cells it owns
+                if (!seg || pos - halo < nout) dj += d;
+            }
+        }
+        J += dj;
+    }
+    shift_to(0);
+#pragma unroll
+    for (int i = 0; i < C; ++i) {
+        if (i < cnt) {
+            const uint32_t pos = off + base_slot + (uint32_t)i;
+            if (!seg || pos - halo < nout) {
+                uint32_t w = base + pos;
+                while (w >= nw) w -= nw;
+                uint64_t* dst = P.words_out + (size_t)ring * NPL * nw;
+                dst[w] = sa[i];
+                if (MODEL == kTwoLane) dst[nw + w] = sb[i];
+            }
+        }
+    }
+    // hops of the ring (whole ring) or of the window's own cells (segments)
+    if (lt == 0 && gi < G) red[gi * 4 + 2] = 0;
+    __syncthreads();
+    if (act) atomicAdd(&red[gi * 4 + 2], (unsigned long long)J);
+    __syncthreads();
+    if (ring_ok && lt == 0) {
+        if (seg)
+            atomicAdd((unsigned long long*)&P.hops[ring], (unsigned long long)red[gi * 4 + 2]);
+        else
+            P.hops[ring] = hops0 + (int64_t)red[gi * 4 + 2];
+    }
+}
+
+// Dispatch of one model's kernels over (C, variant, q0).  Compiled variants:
+// generic for every C; fast (ell = 64) for C <= 8 -- single lane with 5, 4 or
+// 1 fields per word, each with and without backward hops; two lanes with 4 or
+// 1 fields per word.
+template <int MODEL, int C, int V, bool Q>
+inline void launch_one(const SimDesc& one, const SimDesc* descs, uint32_t n_desc, uint32_t grid,
+                       uint32_t block, size_t lds, hipStream_t st) {
+    (void)descs;
+    (void)n_desc;
+    hipLaunchKernelGGL((k_sweep<C, MODEL, V, Q>), dim3(grid), dim3(block), lds, st, one);
+}
+
+template <int MODEL, int C, int V>
+inline void launch_q(const SweepKernel& k, const SimDesc& one, uint32_t grid, uint32_t block,
+                     size_t lds, hipStream_t st) {
+    if (MODEL != kTwoLane && k.q0)
+        launch_one<MODEL, C, V, true>(one, nullptr, 0, grid, block, lds, st);
+    else
+        launch_one<MODEL, C, V, false>(one, nullptr, 0, grid, block, lds, st);
+}
+
+template <int MODEL, int C>
+inline hipError_t launch_c(const SweepKernel& k, const SimDesc& one, const SimDesc* descs,
+                           uint32_t n_desc, uint32_t grid, uint32_t block, size_t lds,
+                           hipStream_t st) {
+    (void)descs;
+    (void)n_desc;
+    if (k.variant == kGeneric) {
+        launch_one<MODEL, C, kGeneric, false>(one, nullptr, 0, grid, block, lds, st);
+        return hipSuccess;
+    }
+    if constexpr (C <= 8) {
+        if constexpr (MODEL == kTwoLane) {
+            switch (k.variant) {
+                case kF4B0: launch_one<MODEL, C, kF4B0, false>(one, nullptr, 0, grid, block, lds, st); return hipSuccess;
+                case kF1: launch_one<MODEL, C, kF1, false>(one, nullptr, 0, grid, block, lds, st); return hipSuccess;
+                default: return hipErrorInvalidValue;
+            }
+        } else {
+            switch (k.variant) {
+                case kF5B0: launch_q<MODEL, C, kF5B0>(k, one, grid, block, lds, st); return hipSuccess;
+                case kF4B1: launch_q<MODEL, C, kF4B1>(k, one, grid, block, lds, st); return hipSuccess;
+                case kF4B2: launch_q<MODEL, C, kF4B2>(k, one, grid, block, lds, st); return hipSuccess;
+                case kF1: launch_q<MODEL, C, kF1>(k, one, grid, block, lds, st); return hipSuccess;
+                default: return hipErrorInvalidValue;
+            }
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int MODEL>
+inline hipError_t launch_model(const SweepKernel& k, const SimDesc& one, const SimDesc* descs,
+                               uint32_t n_desc, uint32_t grid, uint32_t block, size_t lds,
+                               hipStream_t st) {
+    (void)hipGetLastError();  // drop errors left by earlier, unrelated calls
+    hipError_t e;
+    switch (k.C) {
+        case 1: e = launch_c<MODEL, 1>(k, one, descs, n_desc, grid, block, lds, st); break;
+        case 2: e = launch_c<MODEL, 2>(k, one, descs, n_desc, grid, block, lds, st); break;
+        case 4: e = launch_c<MODEL, 4>(k, one, descs, n_desc, grid, block, lds, st); break;
+        case 8: e = launch_c<MODEL, 8>(k, one, descs, n_desc, grid, block, lds, st); break;
+        case 16: e = launch_c<MODEL, 16>(k, one, descs, n_desc, grid, block, lds, st); break;
+        default: e = hipErrorInvalidValue;
+    }
+    if (e != hipSuccess) return e;
+    return hipGetLastError();
+}
+
+// Whether launch_model has a kernel for (C, model, variant).
+inline bool variant_compiled(uint32_t C, uint32_t model, uint32_t variant) {
+    if (C != 1 && C != 2 && C != 4 && C != 8 && C != 16) return false;
+    if (variant == kGeneric) return true;
+    if (C > 8) return false;
+    if (model == kTwoLane) return variant == kF4B0 || variant == kF1;
+    return variant == kF5B0 || variant == kF4B1 || variant == kF4B2 || variant == kF1;
+}
+
+}  // namespace dev
+}  // namespace asep

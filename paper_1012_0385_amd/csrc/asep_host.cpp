@@ -166,94 +166,212 @@ static int resolve(const asep_params* in, Resolved* r) {
     return ASEP_OK;
 }
 
-struct Shape {
-    uint32_t C, lanes_per_ring, rings_per_wg, block, grid;
-    size_t lds;
+// ---------------------------------------------------------------------------
+// Launch plans.  A ring is either held whole by one workgroup (periodic,
+// measurements inside the launch) or cut into windows of seg_n output words
+// plus a halo, one workgroup each, advanced K <= halo-1 sub-sweeps per launch
+// between two state buffers.  Windows are used when the ring does not fit a
+// workgroup, or when whole rings would leave compute units idle.
+// ---------------------------------------------------------------------------
+struct Plan {
+    bool seg = false;
+    uint32_t C = 1, block = 64, lanes_per_ring = 1, rings_per_wg = 1, grid = 1;
+    uint32_t segs = 1, seg_n = 0, halo = 0, nslot = 0, K = 0;
+    size_t lds = 0;
+    SweepKernel kern{};
 };
 
-static size_t lds_limit() {
+static void device_limits(size_t* lds, uint32_t* cus) {
     static size_t lim = 0;
+    static uint32_t ncu = 0;
     if (!lim) {
         int dev = 0;
         hipDeviceProp_t prop;
-        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
             lim = prop.sharedMemPerBlock;
+            ncu = (uint32_t)prop.multiProcessorCount;
+        }
         if (!lim) lim = 65536;
+        if (!ncu) ncu = 256;
     }
-    return lim;
+    *lds = lim;
+    *cus = ncu;
 }
 
-// Launch shape of the register-resident ring kernel.
-static int choose_shape(const Resolved& r, Shape* s) {
-    const uint32_t nw = r.nw;
-    const uint32_t R = r.P.samples;
+// Attempt-loop variant: the specialised ones need ell = 64 and the default
+// four sub-sweeps per MCS (16 attempts per cell and sub-sweep; 64 on two
+// lanes); they differ in fields per 32-bit word and compared bits.
+static SweepKernel pick_kernel(const Resolved& r, uint32_t C) {
+    SweepKernel k{};
+    k.C = C;
+    k.model = r.model;
+    k.variant = 0;
+    const Sched& sc = r.sc;
+    const bool two = r.model == kTwoLane;
+    if (sc.lam == 6 && sc.a == (two ? 64u : 16u)) {
+        uint32_t v = 0;
+        if (!two) {
+            if (sc.A == 5 && sc.b == 0) v = 1;
+            if (sc.A == 4 && sc.b == 1) v = 2;
+            if (sc.A == 4 && sc.b == 2) v = 3;
+            if (sc.A == 1) v = 4;
+        } else {
+            if (sc.A == 4 && sc.b == 0) v = 5;
+            if (sc.A == 1) v = 4;
+        }
+        if (v && sweep_variant_compiled(C, r.model, v)) k.variant = v;
+    }
+    k.q0 = !two && sc.T[1] == 0 && (r.model != kDisorder || sc.T[3] == 0);
+    return k;
+}
+
+static bool plan_whole(const Resolved& r, Plan* p) {
+    size_t lim;
+    uint32_t ncu;
+    device_limits(&lim, &ncu);
+    const uint32_t nw = r.nw, R = r.P.samples;
     static const uint32_t Cs[] = {1, 2, 4, 8, 16};
     for (uint32_t C : Cs) {
-        const uint32_t lim = ring_block_limit(C);
+        const uint32_t maxb = sweep_block_limit(C, r.model);
         const uint32_t Tr = (nw + C - 1) / C;
-        if (Tr > lim) continue;
-        // small rings: pack several per workgroup, up to 256 lanes
+        if (Tr > maxb) continue;
         uint32_t G = 1;
         if (Tr < 256) G = std::max(1u, std::min(256u / Tr, R));
-        const uint32_t lanes = G * Tr;
-        const uint32_t block = std::min(lim, (lanes + 63) / 64 * 64);
-        if (block < lanes) continue;
-        const size_t lds = ring_lds_bytes(block, r.planes, G, r.mplanes, nw);
-        if (lds > lds_limit()) continue;
-        s->C = C;
-        s->lanes_per_ring = Tr;
-        s->rings_per_wg = G;
-        s->block = block;
-        s->grid = (R + G - 1) / G;
-        s->lds = lds;
+        const uint32_t block = std::min(maxb, (G * Tr + 63) / 64 * 64);
+        if (block < G * Tr) continue;
+        const size_t lds = sweep_lds_bytes(block, r.planes, G, r.mplanes, nw);
+        if (lds > lim) continue;
+        p->seg = false;
+        p->C = C;
+        p->block = block;
+        p->lanes_per_ring = Tr;
+        p->rings_per_wg = G;
+        p->grid = (R + G - 1) / G;
+        p->segs = 1;
+        p->lds = lds;
+        p->kern = pick_kernel(r, C);
+        return true;
+    }
+    return false;
+}
+
+static bool plan_windows(const Resolved& r, uint32_t segs, uint32_t K, Plan* p) {
+    size_t lim;
+    uint32_t ncu;
+    device_limits(&lim, &ncu);
+    const uint32_t nw = r.nw;
+    if (segs < 2 || segs > nw) return false;
+    const uint32_t seg_n = (nw + segs - 1) / segs;
+    if ((uint64_t)(segs - 1) * seg_n >= nw) return false;  // every window owns words
+    const uint32_t halo = K + 1;
+    const uint32_t nslot = seg_n + 2 * halo;
+    if (nslot + halo + 2 > 4 * (uint64_t)nw) return false;
+    static const uint32_t Cs[] = {1, 2, 4, 8};
+    for (uint32_t C : Cs) {
+        const uint32_t maxb = sweep_block_limit(C, r.model);
+        const uint32_t Tr = (nslot + C - 1) / C;
+        if (Tr > maxb) continue;
+        const uint32_t block = (Tr + 63) / 64 * 64;
+        if (block > maxb) continue;
+        const size_t lds = sweep_lds_bytes(block, r.planes, 1, r.mplanes, nslot + halo + 2);
+        if (lds > lim) continue;
+        p->seg = true;
+        p->C = C;
+        p->block = block;
+        p->lanes_per_ring = Tr;
+        p->rings_per_wg = 1;
+        p->segs = segs;
+        p->seg_n = seg_n;
+        p->halo = halo;
+        p->nslot = nslot;
+        p->K = K;
+        p->grid = r.P.samples * segs;
+        p->lds = lds;
+        p->kern = pick_kernel(r, C);
+        return true;
+    }
+    return false;
+}
+
+static int choose_plan(const Resolved& r, Plan* p) {
+    size_t lim;
+    uint32_t ncu;
+    device_limits(&lim, &ncu);
+    const uint32_t want = r.P.windows;  // windows per ring (0 = auto)
+    uint32_t K = r.P.window_sweeps ? r.P.window_sweeps : 63;  // sub-sweeps per window launch
+    if (K > 4096) return ASEP_E_INVAL;
+    if (want == 1) return plan_whole(r, p) ? ASEP_OK : ASEP_E_UNSUPPORTED;
+    if (want >= 2) return plan_windows(r, want, K, p) ? ASEP_OK : ASEP_E_UNSUPPORTED;
+    Plan whole;
+    const bool have_whole = plan_whole(r, &whole);
+    const uint32_t R = r.P.samples;
+    if (have_whole) {
+        // windows only pay when whole rings would leave compute units idle and
+        // the rings are long enough for the halo to stay small
+        if (whole.grid >= ncu || r.nw < 16 * (K + 1)) {
+            *p = whole;
+            return ASEP_OK;
+        }
+        const uint32_t segs = (ncu + R - 1) / R;
+        if (segs >= 2 && r.nw / segs >= 8 * (K + 1) && plan_windows(r, segs, K, p)) return ASEP_OK;
+        *p = whole;
         return ASEP_OK;
+    }
+    // rings too long for one workgroup: smallest window count that fits
+    for (uint32_t segs = 2; segs <= r.nw; segs = segs + (segs >> 2) + 1) {
+        uint32_t s2 = std::max(segs, (ncu + R - 1) / R);
+        if (plan_windows(r, s2, K, p)) return ASEP_OK;
     }
     return ASEP_E_UNSUPPORTED;
 }
 
 struct asep_sim {
     Resolved r;
-    Shape shape;
+    Plan plan;
     hipStream_t stream = nullptr;
     bool own_stream = false;
-    uint64_t* words = nullptr;
+    uint64_t* words = nullptr;  // the state buffer (caller-visible)
+    uint64_t* alt = nullptr;    // second state buffer of windowed plans
     uint64_t* masks = nullptr;
     int64_t* hops = nullptr;
-    Record* rec = nullptr;     // device staging
-    uint64_t* rec_t = nullptr; // device copy of measurement times
-    uint32_t rec_cap = 0;      // records per ring the staging holds
+    Record* rec = nullptr;      // device staging
+    uint64_t* rec_g = nullptr;  // device copy of measurement points (sub-sweeps)
+    uint32_t rec_cap = 0;       // records per ring the staging holds
     void* own_state = nullptr;
     void* own_aux = nullptr;
     uint64_t t = 0;
     std::vector<Record> host_rec;
+    std::vector<uint64_t> host_g;
     // sweep-launch timing
     bool prof = false;
-    std::vector<hipEvent_t> ev;     // pairs (start, stop)
-    std::vector<uint64_t> ev_att;   // attempts of each pending pair
-    size_t ev_pending = 0;
+    std::vector<hipEvent_t> ev;    // pairs (start, stop), ring buffer
+    std::vector<uint64_t> ev_att;  // attempts of each recorded pair
+    size_t ev_head = 0, ev_count = 0;
     asep_profile_stats prof_acc{};
 };
 
-static const size_t kEvPairs = 64;
+static const size_t kEvPairs = 4096;
 
-// Add the durations of every recorded (start, stop) pair (waits for them).
-static int harvest_events(asep_sim* s) {
-    for (size_t i = 0; i < s->ev_pending; ++i) {
+// Add the durations of the oldest `n` recorded pairs (waits for them).
+static int harvest_events(asep_sim* s, size_t n) {
+    n = std::min(n, s->ev_count);
+    for (size_t q = 0; q < n; ++q) {
+        const size_t i = (s->ev_head + kEvPairs - s->ev_count) % kEvPairs;
         HIP_OR_FAIL(hipEventSynchronize(s->ev[2 * i + 1]));
         float ms = 0.f;
         HIP_OR_FAIL(hipEventElapsedTime(&ms, s->ev[2 * i], s->ev[2 * i + 1]));
         s->prof_acc.launches += 1;
         s->prof_acc.kernel_ms += ms;
         s->prof_acc.attempts += s->ev_att[i];
+        s->ev_count -= 1;
     }
-    s->ev_pending = 0;
     return ASEP_OK;
 }
 
-static const uint32_t kRecCap = 64;  // measurement times per launch
+static const uint32_t kRecCap = 64;  // measurement times per chunk
 
-static void aux_layout(const Resolved& r, size_t* o_masks, size_t* o_hops, size_t* o_rec,
-                       size_t* o_rect, size_t* total) {
+static void aux_layout(const Resolved& r, const Plan& pl, size_t* o_masks, size_t* o_hops,
+                       size_t* o_rec, size_t* o_recg, size_t* o_alt, size_t* total) {
     size_t off = 0;
     *o_masks = off;
     off += (size_t)r.n_real * r.mplanes * r.nw * 8;
@@ -264,8 +382,11 @@ static void aux_layout(const Resolved& r, size_t* o_masks, size_t* o_hops, size_
     *o_rec = off;
     off += (size_t)kRecCap * r.P.samples * sizeof(Record);
     off = (off + 255) & ~(size_t)255;
-    *o_rect = off;
+    *o_recg = off;
     off += (size_t)kRecCap * 8;
+    off = (off + 255) & ~(size_t)255;
+    *o_alt = off;
+    if (pl.seg) off += (size_t)r.P.samples * r.planes * r.nw * 8;
     *total = (off + 255) & ~(size_t)255;
 }
 
@@ -273,8 +394,11 @@ extern "C" int asep_buffer_sizes(const asep_params* p, size_t* state_bytes, size
     Resolved r;
     int rc = resolve(p, &r);
     if (rc) return rc;
-    size_t a, b, c, d, tot;
-    aux_layout(r, &a, &b, &c, &d, &tot);
+    Plan pl;
+    rc = choose_plan(r, &pl);
+    if (rc) return rc;
+    size_t a, b, c, d, e, tot;
+    aux_layout(r, pl, &a, &b, &c, &d, &e, &tot);
     if (state_bytes) *state_bytes = (size_t)r.P.samples * r.planes * r.nw * 8;
     if (aux_bytes) *aux_bytes = tot;
     return ASEP_OK;
@@ -297,15 +421,14 @@ static int create_common(const asep_params* p, void* state, size_t state_bytes, 
     asep_sim* s = new (std::nothrow) asep_sim();
     if (!s) return ASEP_E_NOMEM;
     int rc = resolve(p, &s->r);
-    if (rc == ASEP_OK) rc = choose_shape(s->r, &s->shape);
+    if (rc == ASEP_OK) rc = choose_plan(s->r, &s->plan);
     if (rc) {
         delete s;
         return rc;
     }
-    size_t need_state, need_aux;
-    asep_buffer_sizes(p, &need_state, &need_aux);
-    size_t o_masks, o_hops, o_rec, o_rect, tot;
-    aux_layout(s->r, &o_masks, &o_hops, &o_rec, &o_rect, &tot);
+    const size_t need_state = (size_t)s->r.P.samples * s->r.planes * s->r.nw * 8;
+    size_t o_masks, o_hops, o_rec, o_recg, o_alt, need_aux;
+    aux_layout(s->r, s->plan, &o_masks, &o_hops, &o_rec, &o_recg, &o_alt, &need_aux);
     if (borrowed) {
         if (!state || !aux || state_bytes < need_state || aux_bytes < need_aux) {
             delete s;
@@ -332,7 +455,8 @@ static int create_common(const asep_params* p, void* state, size_t state_bytes, 
     s->masks = s->r.mplanes ? (uint64_t*)(a + o_masks) : nullptr;
     s->hops = (int64_t*)(a + o_hops);
     s->rec = (Record*)(a + o_rec);
-    s->rec_t = (uint64_t*)(a + o_rect);
+    s->rec_g = (uint64_t*)(a + o_recg);
+    s->alt = s->plan.seg ? (uint64_t*)(a + o_alt) : nullptr;
     s->rec_cap = kRecCap;
     rc = sim_init(s);
     if (rc) {
@@ -369,46 +493,116 @@ extern "C" void asep_destroy(asep_sim* s) {
     delete s;
 }
 
-// One launch of the ring kernel from s->t to t1, measuring at rec_t[0..n).
-static int ring_launch(asep_sim* s, uint64_t t1, const uint64_t* rec_t_dev, uint32_t n_rec) {
+static SimDesc make_desc(const asep_sim* s) {
     const Resolved& r = s->r;
-    RingArgs a{};
-    a.words = s->words;
-    a.masks = s->masks;
-    a.hops = s->hops;
-    a.rec = s->rec;
-    a.rec_t = rec_t_dev;
-    a.n_rec = n_rec;
-    a.t0 = s->t;
-    a.t1 = t1;
-    a.R = r.P.samples;
-    a.nw = r.nw;
-    a.planes = r.planes;
-    a.mplanes = r.mplanes;
-    a.lanes_per_ring = s->shape.lanes_per_ring;
-    a.rings_per_wg = s->shape.rings_per_wg;
-    a.key0 = r.P.seed;
-    a.key1 = r.P.stream;
-    a.sample0 = r.P.sample_offset;
-    a.spd = r.spd;
-    a.real0 = r.real0;
-    a.sc = r.sc;
+    const Plan& pl = s->plan;
+    SimDesc d{};
+    d.words_in = s->words;
+    d.words_out = s->words;
+    d.masks = s->masks;
+    d.hops = s->hops;
+    d.rec = s->rec;
+    d.rec_g = s->rec_g;
+    d.R = r.P.samples;
+    d.nw = r.nw;
+    d.planes = r.planes;
+    d.mplanes = r.mplanes;
+    d.lanes_per_ring = pl.lanes_per_ring;
+    d.rings_per_wg = pl.rings_per_wg;
+    d.segs = pl.segs;
+    d.seg_n = pl.seg_n;
+    d.halo = pl.halo;
+    d.nslot = pl.nslot;
+    d.key0 = r.P.seed;
+    d.key1 = r.P.stream;
+    d.sample0 = r.P.sample_offset;
+    d.spd = r.spd;
+    d.real0 = r.real0;
+    d.wg_begin = 0;
+    d.sc = r.sc;
+    return d;
+}
+
+// One sweep launch on the simulation's stream (timed when profiling).
+static int sweep_launch(asep_sim* s, const SimDesc& d) {
+    const Plan& pl = s->plan;
     const bool prof = s->prof;
+    size_t slot = 0;
     if (prof) {
-        if (s->ev_pending == kEvPairs) {
-            int rc = harvest_events(s);
+        if (s->ev_count == kEvPairs) {
+            int rc = harvest_events(s, kEvPairs / 2);
             if (rc) return rc;
         }
-        HIP_OR_FAIL(hipEventRecord(s->ev[2 * s->ev_pending], s->stream));
+        slot = s->ev_head;
+        HIP_OR_FAIL(hipEventRecord(s->ev[2 * slot], s->stream));
     }
-    HIP_OR_FAIL(launch_ring(a, s->shape.C, r.model, s->shape.block, s->shape.grid, s->shape.lds,
-                            s->stream));
+    HIP_OR_FAIL(launch_sweep(pl.kern, d, nullptr, 0, pl.grid, pl.block, pl.lds, s->stream));
     if (prof) {
-        HIP_OR_FAIL(hipEventRecord(s->ev[2 * s->ev_pending + 1], s->stream));
-        s->ev_att[s->ev_pending] = (t1 - s->t) * (uint64_t)r.P.samples * r.P.L * (r.planes == 2 ? 4 : 1);
-        s->ev_pending += 1;
+        HIP_OR_FAIL(hipEventRecord(s->ev[2 * slot + 1], s->stream));
+        const Resolved& r = s->r;
+        s->ev_att[slot] = (d.g1 - d.g0) * (uint64_t)r.P.samples * r.P.L * (r.planes == 2 ? 4 : 1) /
+                          r.sc.S;
+        s->ev_head = (s->ev_head + 1) % kEvPairs;
+        s->ev_count += 1;
     }
-    s->t = t1;
+    return ASEP_OK;
+}
+
+// Queue the work from the current time to t_end (MCS), measuring at
+// times[0..n) (ascending, within [t, t_end], n <= rec_cap) into the device
+// staging; the records are copied to host_out (n x samples) asynchronously.
+static int enqueue_to(asep_sim* s, uint64_t t_end, const uint64_t* times, uint32_t n,
+                      Record* host_out) {
+    const Resolved& r = s->r;
+    const uint32_t S = r.sc.S;
+    SimDesc d = make_desc(s);
+    if (!s->plan.seg) {
+        if (n) {
+            s->host_g.resize(n);
+            for (uint32_t i = 0; i < n; ++i) s->host_g[i] = times[i] * S;
+            HIP_OR_FAIL(hipMemcpyAsync(s->rec_g, s->host_g.data(), 8 * n, hipMemcpyHostToDevice,
+                                       s->stream));
+        }
+        d.g0 = s->t * S;
+        d.g1 = t_end * S;
+        d.n_rec = n;
+        int rc = sweep_launch(s, d);
+        if (rc) return rc;
+    } else {
+        // windows: launches of at most K sub-sweeps between the two buffers,
+        // measurements from the words of whole rings between launches
+        uint64_t* cur = s->words;
+        uint64_t* oth = s->alt;
+        uint64_t g = s->t * S;
+        const uint64_t g_end = t_end * S;
+        uint32_t ri = 0;
+        for (;;) {
+            while (ri < n && times[ri] * S == g) {
+                HIP_OR_FAIL(launch_rough(cur, s->hops, s->rec + (size_t)ri * r.P.samples,
+                                         r.P.samples, r.planes, r.nw, s->stream));
+                ++ri;
+            }
+            if (g >= g_end) break;
+            uint64_t gl = std::min<uint64_t>(g + s->plan.K, g_end);
+            if (ri < n) gl = std::min<uint64_t>(gl, times[ri] * S);
+            d.words_in = cur;
+            d.words_out = oth;
+            d.g0 = g;
+            d.g1 = gl;
+            d.n_rec = 0;
+            int rc = sweep_launch(s, d);
+            if (rc) return rc;
+            std::swap(cur, oth);
+            g = gl;
+        }
+        if (cur != s->words)
+            HIP_OR_FAIL(hipMemcpyAsync(s->words, cur, (size_t)r.P.samples * r.planes * r.nw * 8,
+                                       hipMemcpyDeviceToDevice, s->stream));
+    }
+    s->t = t_end;
+    if (n && host_out)
+        HIP_OR_FAIL(hipMemcpyAsync(host_out, s->rec, sizeof(Record) * n * r.P.samples,
+                                   hipMemcpyDeviceToHost, s->stream));
     return ASEP_OK;
 }
 
@@ -420,7 +614,7 @@ extern "C" int asep_profile_enable(asep_sim* s, int enable) {
         for (auto& e : s->ev) HIP_OR_FAIL(hipEventCreate(&e));
     }
     if (!enable) {
-        int rc = harvest_events(s);
+        int rc = harvest_events(s, s->ev_count);
         if (rc) return rc;
     }
     s->prof = enable != 0;
@@ -430,7 +624,7 @@ extern "C" int asep_profile_enable(asep_sim* s, int enable) {
 
 extern "C" int asep_profile_read(asep_sim* s, asep_profile_stats* out) {
     if (!s || !out) return ASEP_E_INVAL;
-    int rc = harvest_events(s);
+    int rc = harvest_events(s, s->ev_count);
     if (rc) return rc;
     *out = s->prof_acc;
     return ASEP_OK;
@@ -451,7 +645,7 @@ extern "C" int asep_sweep(asep_sim* s, uint64_t n_mcs) {
     if (n_mcs == 0) return ASEP_OK;
     const uint64_t t1 = s->t + n_mcs;
     if (t1 < s->t || t1 > kMaxG / s->r.sc.S) return ASEP_E_INVAL;
-    return ring_launch(s, t1, nullptr, 0);
+    return enqueue_to(s, t1, nullptr, 0, nullptr);
 }
 
 static void fill_rough(const Resolved& r, const Record& rc, asep_rough* o) {
@@ -478,27 +672,47 @@ extern "C" int asep_roughness(asep_sim* s, asep_rough* out) {
     return ASEP_OK;
 }
 
-extern "C" int asep_run(asep_sim* s, const uint64_t* times, uint32_t n_times, asep_rough* out) {
-    if (!s || (n_times && (!times || !out))) return ASEP_E_INVAL;
+static int check_times(const asep_sim* s, const uint64_t* times, uint32_t n_times) {
     for (uint32_t i = 0; i < n_times; ++i) {
         if (times[i] < s->t || (i && times[i] < times[i - 1])) return ASEP_E_INVAL;
         if (times[i] > kMaxG / s->r.sc.S) return ASEP_E_INVAL;
     }
-    const Resolved& r = s->r;
-    const uint32_t R = r.P.samples;
-    s->host_rec.resize((size_t)s->rec_cap * R);
+    return ASEP_OK;
+}
+
+extern "C" int asep_run(asep_sim* s, const uint64_t* times, uint32_t n_times, asep_rough* out) {
+    asep_sim* one[1] = {s};
+    asep_rough* outs[1] = {out};
+    return asep_run_batch(one, 1, times, n_times, outs);
+}
+
+extern "C" int asep_run_batch(asep_sim* const* sims, uint32_t n_sims, const uint64_t* times,
+                              uint32_t n_times, asep_rough* const* outs) {
+    if (!sims || n_sims == 0 || (n_times && (!times || !outs))) return ASEP_E_INVAL;
+    for (uint32_t k = 0; k < n_sims; ++k) {
+        if (!sims[k] || (n_times && !outs[k])) return ASEP_E_INVAL;
+        for (uint32_t j = 0; j < k; ++j)
+            if (sims[j] == sims[k]) return ASEP_E_INVAL;
+        int rc = check_times(sims[k], times, n_times);
+        if (rc) return rc;
+        sims[k]->host_rec.resize((size_t)sims[k]->rec_cap * sims[k]->r.P.samples);
+    }
     uint32_t done = 0;
     while (done < n_times) {
-        const uint32_t n = std::min(s->rec_cap, n_times - done);
-        HIP_OR_FAIL(hipMemcpyAsync(s->rec_t, times + done, 8 * n, hipMemcpyHostToDevice,
-                                   s->stream));
-        int rc = ring_launch(s, times[done + n - 1], s->rec_t, n);
-        if (rc) return rc;
-        HIP_OR_FAIL(hipMemcpyAsync(s->host_rec.data(), s->rec, sizeof(Record) * n * R,
-                                   hipMemcpyDeviceToHost, s->stream));
-        HIP_OR_FAIL(hipStreamSynchronize(s->stream));
-        for (uint32_t i = 0; i < n * R; ++i)
-            fill_rough(r, s->host_rec[i], &out[(size_t)done * R + i]);
+        const uint32_t n = std::min(kRecCap, n_times - done);
+        // queue every simulation's chunk before waiting on any of them
+        for (uint32_t k = 0; k < n_sims; ++k) {
+            int rc = enqueue_to(sims[k], times[done + n - 1], times + done, n,
+                                sims[k]->host_rec.data());
+            if (rc) return rc;
+        }
+        for (uint32_t k = 0; k < n_sims; ++k) {
+            asep_sim* s = sims[k];
+            HIP_OR_FAIL(hipStreamSynchronize(s->stream));
+            const uint32_t R = s->r.P.samples;
+            for (uint32_t i = 0; i < n * R; ++i)
+                fill_rough(s->r, s->host_rec[i], &outs[k][(size_t)done * R + i]);
+        }
         done += n;
     }
     return ASEP_OK;
@@ -514,22 +728,13 @@ uint64_t sim_attempts_per_mcs(const asep_sim* s) {
     return (uint64_t)s->r.P.samples * s->r.P.L * (s->r.planes == 2 ? 4 : 1);
 }
 
-// Queue one launch advancing to t_end and measuring at times[0..n) (n <= the
+// Queue the work advancing to t_end and measuring at times[0..n) (n <= the
 // record capacity, every time in [asep_time, t_end]); the records are copied
 // asynchronously to host_out (n x samples).
-int sim_run_async(asep_sim* s, const uint64_t* times_pinned, uint32_t n, uint64_t t_end,
+int sim_run_async(asep_sim* s, const uint64_t* times, uint32_t n, uint64_t t_end,
                   Record* host_out) {
     if (n > s->rec_cap || t_end < s->t) return ASEP_E_INVAL;
-    if (n) {
-        HIP_OR_FAIL(hipMemcpyAsync(s->rec_t, times_pinned, 8 * n, hipMemcpyHostToDevice,
-                                   s->stream));
-    }
-    int rc = ring_launch(s, t_end, s->rec_t, n);
-    if (rc) return rc;
-    if (n)
-        HIP_OR_FAIL(hipMemcpyAsync(host_out, s->rec, sizeof(Record) * n * s->r.P.samples,
-                                   hipMemcpyDeviceToHost, s->stream));
-    return ASEP_OK;
+    return enqueue_to(s, t_end, times, n, host_out);
 }
 
 void record_to_rough(const asep_sim* s, const Record& rc, asep_rough* o) { fill_rough(s->r, rc, o); }

@@ -41,38 +41,60 @@ struct Sched {
 
 enum Model : uint32_t { kPlain = 0, kDisorder = 1, kTwoLane = 2 };
 
-// Arguments of the register-resident ring kernel.
-struct RingArgs {
-    uint64_t* words;          // [R][planes][nw]
-    const uint64_t* masks;    // [realizations][mplanes][nw] or null
+// Work of one simulation inside one sweep launch.
+struct SimDesc {
+    uint64_t* words_in;       // [R][planes][nw] state read by the launch
+    uint64_t* words_out;      // state written (== words_in for whole rings)
+    const uint64_t* masks;    // [realisations][mplanes][nw], first = real0
     int64_t* hops;            // [R]
-    Record* rec;              // [n_rec][R] or null
-    const uint64_t* rec_t;    // [n_rec] absolute MCS, ascending, in [t0, t1]
+    Record* rec;              // [n_rec][R] (whole rings only)
+    const uint64_t* rec_g;    // [n_rec] sub-sweep indices of measurements, in [g0, g1]
+    uint64_t g0, g1;          // sub-sweeps [g0, g1) of this launch
     uint32_t n_rec;
-    uint64_t t0, t1;
     uint32_t R, nw, planes, mplanes;
-    uint32_t lanes_per_ring;  // lanes serving one ring
-    uint32_t rings_per_wg;
-    uint32_t key0, key1, sample0, spd;
-    uint32_t real0;           // first realisation held in masks
+    uint32_t lanes_per_ring;  // lanes serving one ring (whole rings) or one window
+    uint32_t rings_per_wg;    // whole rings packed per workgroup (1 for windows)
+    uint32_t segs;            // windows per ring (1 = whole ring, periodic)
+    uint32_t seg_n;           // output words per window
+    uint32_t halo;            // words of context on each side of a window
+    uint32_t nslot;           // slots of a window (seg_n + 2 halo)
+    uint32_t key0, key1, sample0, spd, real0;
+    uint32_t wg_begin;        // first workgroup of this simulation in a batched launch
     Sched sc;
 };
 
-// Host-side launch helpers implemented in asep_kernels.hip.
+// Host-side launch helpers implemented in the .hip translation units.
 hipError_t launch_init_state(uint64_t* words, uint32_t R, uint32_t planes, uint32_t nw,
                              uint32_t init, uint64_t T_init, uint32_t key0, uint32_t key1,
                              uint32_t sample0, hipStream_t st);
 hipError_t launch_init_masks(uint64_t* masks, uint32_t n_real, uint32_t mplanes,
                              const uint32_t* tags, uint32_t nw, uint64_t T, uint32_t key0,
                              uint32_t key1, uint32_t real0, hipStream_t st);
-// C slots (64-bit words) per lane, model; dynamic LDS bytes in *lds.
-hipError_t launch_ring(const RingArgs& a, uint32_t C, uint32_t model, uint32_t block,
-                       uint32_t grid, size_t lds, hipStream_t st);
-uint32_t ring_block_limit(uint32_t C);
-size_t ring_lds_bytes(uint32_t block, uint32_t planes, uint32_t rings_per_wg, uint32_t mplanes,
-                      uint32_t nw);
 hipError_t launch_rough(const uint64_t* words, const int64_t* hops, Record* rec, uint32_t R,
                         uint32_t planes, uint32_t nw, hipStream_t st);
+
+// Sweep launch: `one` describes the whole launch when descs == nullptr;
+// otherwise descs[0..n_desc) (device memory, sorted by wg_begin) do.
+struct SweepKernel {
+    uint32_t C, model, variant;
+    bool q0;
+};
+hipError_t launch_sweep(const SweepKernel& k, const SimDesc& one, const SimDesc* descs,
+                        uint32_t n_desc, uint32_t grid, uint32_t block, size_t lds,
+                        hipStream_t st);
+hipError_t launch_sweep_plain(const SweepKernel& k, const SimDesc& one, const SimDesc* descs,
+                              uint32_t n_desc, uint32_t grid, uint32_t block, size_t lds,
+                              hipStream_t st);
+hipError_t launch_sweep_disorder(const SweepKernel& k, const SimDesc& one, const SimDesc* descs,
+                                 uint32_t n_desc, uint32_t grid, uint32_t block, size_t lds,
+                                 hipStream_t st);
+hipError_t launch_sweep_two_lane(const SweepKernel& k, const SimDesc& one, const SimDesc* descs,
+                                 uint32_t n_desc, uint32_t grid, uint32_t block, size_t lds,
+                                 hipStream_t st);
+uint32_t sweep_block_limit(uint32_t C, uint32_t model);
+size_t sweep_lds_bytes(uint32_t block, uint32_t planes, uint32_t rings_per_wg, uint32_t mplanes,
+                       uint32_t mwords);
+bool sweep_variant_compiled(uint32_t C, uint32_t model, uint32_t variant);
 
 }  // namespace asep
 

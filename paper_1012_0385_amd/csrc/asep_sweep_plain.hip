@@ -1,0 +1,13 @@
+// asep_sweep_plain.hip -- instantiations of the sweep kernel for the
+// plain model (one translation unit per model so that they compile in parallel).
+#include "asep_device.h"
+
+namespace asep {
+
+hipError_t launch_sweep_plain(const SweepKernel& k, const SimDesc& one, const SimDesc* descs,
+                                uint32_t n_desc, uint32_t grid, uint32_t block, size_t lds,
+                                hipStream_t st) {
+    return dev::launch_model<kPlain>(k, one, descs, n_desc, grid, block, lds, st);
+}
+
+}  // namespace asep

@@ -19,7 +19,8 @@ def make_params(L: int, samples: int = 1, *, model: int = B.ASEP_MODEL_RING,
                 q: float = 0.0, slow_frac: float = 0.0, slow_factor: float = 1.0,
                 samples_per_disorder: int = 1, lane_rate: float = 0.0, turn_frac: float = 0.0,
                 seed: int = 1, stream: int = 0, cell_log2: int = 0, subsweeps: int = 0,
-                rbits: int = -1, sample_offset: int = 0) -> B.asep_params:
+                rbits: int = -1, sample_offset: int = 0, windows: int = 0,
+                window_sweeps: int = 0) -> B.asep_params:
     P = B.asep_params()
     P.abi_version = B.ASEP_ABI_VERSION
     P.model = model
@@ -40,6 +41,8 @@ def make_params(L: int, samples: int = 1, *, model: int = B.ASEP_MODEL_RING,
     P.cell_log2 = cell_log2
     P.subsweeps = subsweeps
     P.rbits = rbits
+    P.windows = windows
+    P.window_sweeps = window_sweeps
     return P
 
 
@@ -188,6 +191,28 @@ class Simulation:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def run_batch(sims, times) -> list:
+    """asep_run_batch: advance several simulations through the same times
+    concurrently; returns one list of Rough (per time) per simulation."""
+    times = [int(t) for t in times]
+    n = len(times)
+    tarr = (ctypes.c_uint64 * max(n, 1))(*times)
+    handles = (ctypes.c_void_p * len(sims))(*[s.handle.value for s in sims])
+    bufs = [(B.asep_rough * max(n * s.samples, 1))() for s in sims]
+    outs = (ctypes.POINTER(B.asep_rough) * len(sims))(
+        *[ctypes.cast(b, ctypes.POINTER(B.asep_rough)) for b in bufs])
+    B.check(B.load().asep_run_batch(handles, len(sims), tarr, n, outs), "asep_run_batch")
+    res = []
+    for s, buf in zip(sims, bufs):
+        per = []
+        for i in range(n):
+            sub = (B.asep_rough * s.samples).from_address(
+                ctypes.addressof(buf) + i * s.samples * ctypes.sizeof(B.asep_rough))
+            per.append(_rough_arrays(sub, s.samples))
+        res.append(per)
+    return res
 
 
 def sample_times(t0: float, factor: float, t_max: int, cap: int = 100000) -> list:

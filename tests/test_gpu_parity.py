@@ -215,6 +215,57 @@ def test_largest_register_ring(orc):
     compare(orc, dict(L=1 << 19, p=1.0, q=0.0, seed=2, stream=5), [0, 2], 1)
 
 
+# --------------------------------------------------------------------------- windows (HBM tier)
+@pytest.mark.parametrize("L,windows,K,S,p,q", [
+    (4096, 2, 3, 4, 1.0, 0.0),     # 64 words in 2 windows, 3 sub-sweeps per launch
+    (4096, 3, 7, 4, 0.5, 0.5),     # ragged last window
+    (8192, 4, 13, 16, 0.8, 0.1),   # general thresholds, launches end mid-MCS
+    (6400, 5, 1, 1, 0.75, 0.25),   # one sub-sweep per launch
+    (16384, 2, 63, 4, 1.0, 0.0),   # default launch length
+])
+def test_windowed_rings(orc, L, windows, K, S, p, q):
+    kw = dict(L=L, p=p, q=q, subsweeps=S, seed=3, stream=7, init=1, density=0.45,
+              windows=windows, window_sweeps=K)
+    compare(orc, kw, [0, 1, 3, 10, 11], 3)
+
+
+def test_windowed_disorder_and_two_lane(orc):
+    kw = dict(L=8192, p=0.75, q=0.5, slow_frac=0.2, slow_factor=0.5, samples_per_disorder=2,
+              seed=3, stream=2, windows=3, window_sweeps=9)
+    compare(orc, kw, [0, 7, 15], 4)
+    kw = dict(L=4096, model=1, init=1, density=0.3, p=1.0, q=1.0, lane_rate=0.1,
+              turn_frac=0.05, seed=1, stream=3, windows=2, window_sweeps=5)
+    compare(orc, kw, [0, 3, 8], 3)
+
+
+def test_windowed_equals_whole(orc):
+    # the launch shape never changes a result
+    base = dict(L=32768, p=1.0, q=0.0, seed=4, stream=1)
+    a = compare(orc, dict(base, windows=1), [0, 5, 9], 2)
+    b = compare(orc, dict(base, windows=4, window_sweeps=11), [0, 5, 9], 2)
+    for x, y in zip(a, b):
+        assert np.array_equal(x.S1, y.S1) and x.S2 == y.S2 and np.array_equal(x.J, y.J)
+
+
+def test_hbm_ring_2p21(orc):
+    # a ring too long for one workgroup: 2^21 sites, automatic windows
+    compare(orc, dict(L=1 << 21, p=1.0, q=0.0, seed=2, stream=5), [0, 1, 3], 1)
+
+
+def test_run_batch_equals_alone(orc):
+    kws = [dict(L=4096, p=1.0, q=0.0, seed=1, stream=0), dict(L=4096, p=0.5, q=0.5, seed=1, stream=1),
+           dict(L=65536, p=1.0, q=0.0, seed=2, stream=2, windows=2, window_sweeps=17)]
+    times = [0, 2, 9, 30]
+    sims = [A.Simulation(A.make_params(samples=3, **kw), stream=torch.cuda.Stream()) for kw in kws]
+    got = A.run_batch(sims, times)
+    for kw, g in zip(kws, got):
+        alone = compare(orc, kw, times, 3)
+        for x, y in zip(g, alone):
+            assert np.array_equal(x.S1, y.S1) and x.S2 == y.S2 and np.array_equal(x.J, y.J)
+    for s in sims:
+        s.close()
+
+
 def test_invalid_parameters_rejected():
     lib = B.load()
     bad = [dict(L=100), dict(L=64, cell_log2=6), dict(L=1024, p=1.5), dict(L=1024, subsweeps=3),
