@@ -195,7 +195,10 @@ int asep_profile_read(asep_sim* s, asep_profile_stats* out);
 uint64_t asep_time(const asep_sim* s);
 
 /* Free library-owned memory and the library-owned stream; borrowed buffers
- * and streams are left alone.  NULL is ignored. */
+ * and streams are left alone.  With a library-owned stream the call first
+ * waits for the simulation's work; with a borrowed stream the caller must
+ * have synchronised it (or an event after the last call) before freeing the
+ * borrowed buffers.  NULL is ignored. */
 void asep_destroy(asep_sim* s);
 
 /* Ensemble mean of W^2 over n records of one time: sum of the exact numerators

@@ -7,6 +7,6 @@ and fails loudly if the library has not been built.
 """
 from . import binding
 from .binding import AsepError
-from .sim import Simulation, ensemble_w2, make_params, run_batch, sample_times
+from .sim import Server, Simulation, ensemble_w2, make_params, run_batch, sample_times
 
-__all__ = ["binding", "AsepError", "Simulation", "ensemble_w2", "make_params", "run_batch", "sample_times"]
+__all__ = ["binding", "AsepError", "Server", "Simulation", "ensemble_w2", "make_params", "run_batch", "sample_times"]

@@ -335,13 +335,11 @@ struct asep_sim {
     uint64_t* masks = nullptr;
     int64_t* hops = nullptr;
     Record* rec = nullptr;      // device staging
-    uint64_t* rec_g = nullptr;  // device copy of measurement points (sub-sweeps)
     uint32_t rec_cap = 0;       // records per ring the staging holds
     void* own_state = nullptr;
     void* own_aux = nullptr;
     uint64_t t = 0;
-    std::vector<Record> host_rec;
-    std::vector<uint64_t> host_g;
+    Record* host_rec = nullptr;  // pinned staging of rec_cap x samples records
     // sweep-launch timing
     bool prof = false;
     std::vector<hipEvent_t> ev;    // pairs (start, stop), ring buffer
@@ -455,7 +453,13 @@ static int create_common(const asep_params* p, void* state, size_t state_bytes, 
     s->masks = s->r.mplanes ? (uint64_t*)(a + o_masks) : nullptr;
     s->hops = (int64_t*)(a + o_hops);
     s->rec = (Record*)(a + o_rec);
-    s->rec_g = (uint64_t*)(a + o_recg);
+    (void)o_recg;
+    if (hipHostMalloc((void**)&s->host_rec, sizeof(Record) * (size_t)kRecCap * s->r.P.samples) !=
+        hipSuccess) {
+        s->host_rec = nullptr;
+        asep_destroy(s);
+        return ASEP_E_NOMEM;
+    }
     s->alt = s->plan.seg ? (uint64_t*)(a + o_alt) : nullptr;
     s->rec_cap = kRecCap;
     rc = sim_init(s);
@@ -485,7 +489,9 @@ extern "C" int asep_get_params(const asep_sim* s, asep_params* out) {
 
 extern "C" void asep_destroy(asep_sim* s) {
     if (!s) return;
-    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    // work queued on a borrowed stream is the caller's to wait for
+    if (s->own_stream && s->stream) (void)hipStreamSynchronize(s->stream);
+    if (s->host_rec) (void)hipHostFree(s->host_rec);
     for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
     if (s->own_state) (void)hipFree(s->own_state);
     if (s->own_aux) (void)hipFree(s->own_aux);
@@ -502,7 +508,6 @@ static SimDesc make_desc(const asep_sim* s) {
     d.masks = s->masks;
     d.hops = s->hops;
     d.rec = s->rec;
-    d.rec_g = s->rec_g;
     d.R = r.P.samples;
     d.nw = r.nw;
     d.planes = r.planes;
@@ -557,12 +562,7 @@ static int enqueue_to(asep_sim* s, uint64_t t_end, const uint64_t* times, uint32
     const uint32_t S = r.sc.S;
     SimDesc d = make_desc(s);
     if (!s->plan.seg) {
-        if (n) {
-            s->host_g.resize(n);
-            for (uint32_t i = 0; i < n; ++i) s->host_g[i] = times[i] * S;
-            HIP_OR_FAIL(hipMemcpyAsync(s->rec_g, s->host_g.data(), 8 * n, hipMemcpyHostToDevice,
-                                       s->stream));
-        }
+        for (uint32_t i = 0; i < n; ++i) d.rec_g[i] = times[i] * S;
         d.g0 = s->t * S;
         d.g1 = t_end * S;
         d.n_rec = n;
@@ -664,8 +664,7 @@ extern "C" int asep_roughness(asep_sim* s, asep_rough* out) {
     if (!s || !out) return ASEP_E_INVAL;
     const Resolved& r = s->r;
     HIP_OR_FAIL(launch_rough(s->words, s->hops, s->rec, r.P.samples, r.planes, r.nw, s->stream));
-    s->host_rec.resize(r.P.samples);
-    HIP_OR_FAIL(hipMemcpyAsync(s->host_rec.data(), s->rec, sizeof(Record) * r.P.samples,
+    HIP_OR_FAIL(hipMemcpyAsync(s->host_rec, s->rec, sizeof(Record) * r.P.samples,
                                hipMemcpyDeviceToHost, s->stream));
     HIP_OR_FAIL(hipStreamSynchronize(s->stream));
     for (uint32_t i = 0; i < r.P.samples; ++i) fill_rough(r, s->host_rec[i], &out[i]);
@@ -695,7 +694,6 @@ extern "C" int asep_run_batch(asep_sim* const* sims, uint32_t n_sims, const uint
             if (sims[j] == sims[k]) return ASEP_E_INVAL;
         int rc = check_times(sims[k], times, n_times);
         if (rc) return rc;
-        sims[k]->host_rec.resize((size_t)sims[k]->rec_cap * sims[k]->r.P.samples);
     }
     uint32_t done = 0;
     while (done < n_times) {
@@ -703,7 +701,7 @@ extern "C" int asep_run_batch(asep_sim* const* sims, uint32_t n_sims, const uint
         // queue every simulation's chunk before waiting on any of them
         for (uint32_t k = 0; k < n_sims; ++k) {
             int rc = enqueue_to(sims[k], times[done + n - 1], times + done, n,
-                                sims[k]->host_rec.data());
+                                sims[k]->host_rec);
             if (rc) return rc;
         }
         for (uint32_t k = 0; k < n_sims; ++k) {

@@ -41,6 +41,9 @@ struct Sched {
 
 enum Model : uint32_t { kPlain = 0, kDisorder = 1, kTwoLane = 2 };
 
+// Measurement points one launch can hold (they travel in the kernel arguments).
+constexpr uint32_t kRecPerLaunch = 64;
+
 // Work of one simulation inside one sweep launch.
 struct SimDesc {
     uint64_t* words_in;       // [R][planes][nw] state read by the launch
@@ -48,7 +51,6 @@ struct SimDesc {
     const uint64_t* masks;    // [realisations][mplanes][nw], first = real0
     int64_t* hops;            // [R]
     Record* rec;              // [n_rec][R] (whole rings only)
-    const uint64_t* rec_g;    // [n_rec] sub-sweep indices of measurements, in [g0, g1]
     uint64_t g0, g1;          // sub-sweeps [g0, g1) of this launch
     uint32_t n_rec;
     uint32_t R, nw, planes, mplanes;
@@ -61,6 +63,7 @@ struct SimDesc {
     uint32_t key0, key1, sample0, spd, real0;
     uint32_t wg_begin;        // first workgroup of this simulation in a batched launch
     Sched sc;
+    uint64_t rec_g[kRecPerLaunch];  // sub-sweep indices of the measurements, in [g0, g1]
 };
 
 // Host-side launch helpers implemented in the .hip translation units.

@@ -3,19 +3,21 @@
 // A request is an ensemble run (parameters, ascending measurement times,
 // t_max), the unit the paper's host driver loops over (Sec. 2.1: blocks of
 // independent realisations, then an outer statistics loop averaging W^2 on
-// the CPU).  Here requests arrive at any time: a worker thread admits them
-// while device memory (the configured budget) and resident slots allow, gives
-// each its own simulation and stream, and advances every resident request by
-// one quantum of MCS per round, all rounds' launches queued before the worker
-// waits on any of them, so the work of different requests overlaps on the
-// GPU.  A request that finishes frees its memory at once and the next
-// arrival is admitted in the same round.  Every random number is keyed by the
-// request's own (seed, stream, sample), and chunking never changes a result,
-// so each request's output is the same alone or in any mix.
+// the CPU).  Requests arrive at any time.  A worker thread admits them in
+// arrival order while the device arena (the configured memory budget) has
+// room for their state and the resident count allows, places each on one of
+// a fixed pool of streams, and advances every resident request by quanta of
+// MCS: as soon as a request's previous quantum has finished (an event per
+// request), its next one is queued, so requests of every size overlap on the
+// GPU and a request that finishes frees its memory for the next arrival at
+// once.  Every random number is keyed by the request's own (seed, stream,
+// sample), and splitting a run into quanta never changes a result, so each
+// request's output is the same alone or in any mix.
 #include <hip/hip_runtime.h>
 #include <time.h>
 
 #include <algorithm>
+#include <chrono>
 #include <condition_variable>
 #include <cstdlib>
 #include <cstring>
@@ -40,24 +42,89 @@ uint64_t now_ns() {
     return (uint64_t)ts.tv_sec * 1000000000ull + (uint64_t)ts.tv_nsec;
 }
 
+// First-fit allocator over one device buffer; blocks are 256-byte aligned.
+class Arena {
+   public:
+    bool init(size_t bytes) {
+        if (hipMalloc(&base_, bytes) != hipSuccess) return false;
+        size_ = bytes;
+        free_[0] = bytes;
+        return true;
+    }
+    void release() {
+        if (base_) (void)hipFree(base_);
+        base_ = nullptr;
+    }
+    void* alloc(size_t bytes) {
+        bytes = (bytes + 255) & ~(size_t)255;
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                const size_t off = it->first;
+                const size_t rest = it->second - bytes;
+                free_.erase(it);
+                if (rest) free_[off + bytes] = rest;
+                used_[off] = bytes;
+                return (char*)base_ + off;
+            }
+        }
+        return nullptr;
+    }
+    void free(void* p) {
+        if (!p) return;
+        const size_t off = (size_t)((char*)p - (char*)base_);
+        auto u = used_.find(off);
+        if (u == used_.end()) return;
+        size_t len = u->second;
+        used_.erase(u);
+        size_t start = off;
+        auto next = free_.lower_bound(off);
+        if (next != free_.end() && next->first == off + len) {
+            len += next->second;
+            next = free_.erase(next);
+        }
+        if (next != free_.begin()) {
+            auto prev = std::prev(next);
+            if (prev->first + prev->second == start) {
+                start = prev->first;
+                len += prev->second;
+                free_.erase(prev);
+            }
+        }
+        free_[start] = len;
+    }
+    size_t size() const { return size_; }
+
+   private:
+    void* base_ = nullptr;
+    size_t size_ = 0;
+    std::map<size_t, size_t> free_;  // offset -> length
+    std::map<size_t, size_t> used_;
+};
+
 struct Job {
     uint64_t ticket = 0;
     asep_params params{};
     uint64_t t_max = 0;
     std::vector<uint64_t> times;
-    size_t footprint = 0;
-    // progress
+    size_t state_bytes = 0, aux_bytes = 0;
+    // resident state
     asep_sim* sim = nullptr;
+    void* state = nullptr;
+    void* aux = nullptr;
+    hipStream_t stream = nullptr;
+    hipEvent_t done_ev = nullptr;
+    Record* pinned_rec = nullptr;
+    bool inflight = false;
     uint32_t next_time = 0;  // first measurement not yet queued
-    std::vector<asep_rough> rough;
-    uint64_t* pinned_times = nullptr;  // host-pinned copy of times
-    Record* pinned_rec = nullptr;      // host-pinned record staging for one round
     uint32_t staged_first = 0, staged_n = 0;
+    std::vector<asep_rough> rough;
     bool cancel = false;
     int status = ASEP_E_PENDING;
     uint64_t t_arrive = 0, t_admit = 0, t_start = 0, t_done = 0;
     uint64_t updates = 0;
 };
+
+const uint32_t kStreams = 8;
 
 }  // namespace
 
@@ -70,145 +137,200 @@ struct asep_server {
     std::vector<std::shared_ptr<Job>> active;
     std::map<uint64_t, std::shared_ptr<Job>> all;  // every ticket not yet collected
     uint64_t next_ticket = 1;
-    size_t in_use = 0;
     bool stop = false;
     std::thread worker;
+    // worker-owned device resources
+    Arena arena;
+    hipStream_t streams[kStreams] = {};
+    uint32_t next_stream = 0;
+    int init_rc = ASEP_OK;
 };
 
 namespace {
 
-void free_job_device(Job& j) {
+void release_job(asep_server* S, Job& j) {
     if (j.sim) {
-        asep_destroy(j.sim);
+        asep_destroy(j.sim);  // the job's work is complete (its event was reached)
         j.sim = nullptr;
     }
-    if (j.pinned_times) (void)hipHostFree(j.pinned_times);
+    S->arena.free(j.state);
+    S->arena.free(j.aux);
+    j.state = j.aux = nullptr;
+    if (j.done_ev) (void)hipEventDestroy(j.done_ev);
+    j.done_ev = nullptr;
     if (j.pinned_rec) (void)hipHostFree(j.pinned_rec);
-    j.pinned_times = nullptr;
     j.pinned_rec = nullptr;
 }
 
-// Create the job's simulation; ASEP_E_NOMEM leaves it queued.
+// Place the job in the arena and create its simulation; ASEP_E_NOMEM means
+// "not now" (no room yet).
 int admit(asep_server* S, Job& j) {
-    int rc = asep_create(&j.params, &j.sim);
-    if (rc) return rc;
-    const uint32_t cap = sim_record_capacity(j.sim);
-    const uint32_t R = sim_samples(j.sim);
-    if (hipHostMalloc((void**)&j.pinned_times, 8 * std::max<size_t>(j.times.size(), 1)) !=
-            hipSuccess ||
-        hipHostMalloc((void**)&j.pinned_rec, sizeof(Record) * (size_t)cap * R) != hipSuccess) {
-        free_job_device(j);
+    j.state = S->arena.alloc(j.state_bytes);
+    j.aux = j.state ? S->arena.alloc(j.aux_bytes) : nullptr;
+    if (!j.state || !j.aux) {
+        S->arena.free(j.state);
+        j.state = nullptr;
         return ASEP_E_NOMEM;
     }
-    if (!j.times.empty()) std::memcpy(j.pinned_times, j.times.data(), 8 * j.times.size());
-    j.rough.assign(j.times.size() * (size_t)R, asep_rough{});
+    j.stream = S->streams[S->next_stream++ % kStreams];
+    int rc = asep_create_ext(&j.params, j.state, j.state_bytes, j.aux, j.aux_bytes, j.stream,
+                             &j.sim);
+    if (rc == ASEP_OK &&
+        hipEventCreateWithFlags(&j.done_ev, hipEventDisableTiming) != hipSuccess)
+        rc = ASEP_E_DEVICE;
+    if (rc == ASEP_OK &&
+        hipHostMalloc((void**)&j.pinned_rec,
+                      sizeof(Record) * sim_record_capacity(j.sim) * j.params.samples) !=
+            hipSuccess) {
+        j.pinned_rec = nullptr;
+        rc = ASEP_E_NOMEM;
+    }
+    if (rc) {
+        if (j.sim && j.stream) (void)hipStreamSynchronize(j.stream);
+        release_job(S, j);
+        return rc == ASEP_E_NOMEM ? ASEP_E_DEVICE : rc;
+    }
+    j.rough.assign(j.times.size() * (size_t)j.params.samples, asep_rough{});
     j.t_admit = now_ns();
-    (void)S;
+    // the initialisation kernels are the job's first work in flight
+    if (hipEventRecord(j.done_ev, j.stream) != hipSuccess) {
+        (void)hipStreamSynchronize(j.stream);
+        release_job(S, j);
+        return ASEP_E_DEVICE;
+    }
+    j.inflight = true;
     return ASEP_OK;
 }
 
-// Queue one round of work for a job; returns an error code or ASEP_OK.
-int queue_round(asep_server* S, Job& j) {
+// Queue the job's next quantum and record its event.
+int queue_quantum(asep_server* S, Job& j) {
     const uint64_t t = asep_time(j.sim);
     const uint64_t q = std::max<uint64_t>(S->cfg.quantum_mcs, 1);
     uint64_t t_end = std::min(j.t_max, t + q);
     const uint32_t cap = sim_record_capacity(j.sim);
-    // measurements due in [t, t_end], at most one launch's worth per round
     uint32_t n = 0;
     while (j.next_time + n < j.times.size() && j.times[j.next_time + n] <= t_end && n < cap) ++n;
     if (n == cap && j.next_time + n < j.times.size() && j.times[j.next_time + n] <= t_end)
         t_end = j.times[j.next_time + n - 1];
     if (!j.t_start) j.t_start = now_ns();
-    int rc = sim_run_async(j.sim, j.pinned_times + j.next_time, n, t_end, j.pinned_rec);
+    int rc = sim_run_async(j.sim, j.times.data() + j.next_time, n, t_end, j.pinned_rec);
     if (rc) return rc;
+    if (hipEventRecord(j.done_ev, j.stream) != hipSuccess) return ASEP_E_DEVICE;
     j.updates += (t_end - t) * sim_attempts_per_mcs(j.sim);
     j.staged_first = j.next_time;
     j.staged_n = n;
     j.next_time += n;
+    j.inflight = true;
     return ASEP_OK;
 }
 
-void collect_round(Job& j) {
+void collect_quantum(Job& j) {
     const uint32_t R = sim_samples(j.sim);
     for (uint32_t i = 0; i < j.staged_n * R; ++i)
         record_to_rough(j.sim, j.pinned_rec[i], &j.rough[(size_t)j.staged_first * R + i]);
     j.staged_n = 0;
+    j.inflight = false;
+}
+
+bool finished(const Job& j) {
+    return asep_time(j.sim) >= j.t_max && j.next_time >= j.times.size();
 }
 
 void finish(asep_server* S, Job& j, int status) {
     j.status = status;
     j.t_done = now_ns();
-    free_job_device(j);
-    S->in_use -= std::min(S->in_use, j.footprint);
+    release_job(S, j);
 }
 
 void worker_main(asep_server* S) {
-    (void)hipSetDevice(S->cfg.device);
+    if (hipSetDevice(S->cfg.device) != hipSuccess) S->init_rc = ASEP_E_DEVICE;
+    for (uint32_t i = 0; i < kStreams && S->init_rc == ASEP_OK; ++i)
+        if (hipStreamCreateWithFlags(&S->streams[i], hipStreamNonBlocking) != hipSuccess)
+            S->init_rc = ASEP_E_DEVICE;
+    if (S->init_rc == ASEP_OK && !S->arena.init(S->cfg.hbm_budget_bytes)) S->init_rc = ASEP_E_NOMEM;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->cv_done.notify_all();
+    }
     std::unique_lock<std::mutex> lk(S->mu);
-    while (!S->stop) {
-        // admission: FIFO while slots and the memory budget allow
+    while (!S->stop && S->init_rc == ASEP_OK) {
+        bool progressed = false;
+        // admission in arrival order while slots and memory allow
         while (!S->queue.empty() && S->active.size() < S->cfg.max_active) {
             auto j = S->queue.front();
+            S->queue.pop_front();
             if (j->cancel) {
-                S->queue.pop_front();
                 finish(S, *j, ASEP_E_CANCELLED);
-                S->cv_done.notify_all();
+                progressed = true;
                 continue;
             }
-            if (S->in_use + j->footprint > S->cfg.hbm_budget_bytes && !S->active.empty()) break;
-            S->queue.pop_front();
-            S->in_use += j->footprint;
-            lk.unlock();
             int rc = admit(S, *j);
-            lk.lock();
-            if (rc == ASEP_E_NOMEM && !S->active.empty()) {
-                S->in_use -= j->footprint;
-                S->queue.push_front(j);  // back-pressure: retry when memory frees
+            if (rc == ASEP_E_NOMEM) {
+                if (S->active.empty()) {
+                    finish(S, *j, ASEP_E_NOMEM);  // can never fit
+                    progressed = true;
+                    continue;
+                }
+                S->queue.push_front(j);  // back-pressure: wait for memory to free
                 break;
             }
             if (rc) {
                 finish(S, *j, rc);
-                S->cv_done.notify_all();
+                progressed = true;
                 continue;
             }
             S->active.push_back(j);
+            progressed = true;
         }
-        if (S->active.empty()) {
-            S->cv_work.wait_for(lk, std::chrono::milliseconds(50));
-            continue;
-        }
-        // one round: queue every active job's quantum, then wait for all
-        std::vector<std::shared_ptr<Job>> round = S->active;
-        lk.unlock();
-        std::vector<int> rcs(round.size(), ASEP_OK);
-        for (size_t i = 0; i < round.size(); ++i)
-            if (!round[i]->cancel) rcs[i] = queue_round(S, *round[i]);
-        for (size_t i = 0; i < round.size(); ++i) {
-            hipError_t e = hipStreamSynchronize(sim_stream(round[i]->sim));
-            if (e != hipSuccess && rcs[i] == ASEP_OK) rcs[i] = device_error(e, "round");
-            if (rcs[i] == ASEP_OK) collect_round(*round[i]);
-        }
-        lk.lock();
+        // progress: every request whose quantum is done gets its next one
         std::vector<std::shared_ptr<Job>> still;
-        for (size_t i = 0; i < round.size(); ++i) {
-            Job& j = *round[i];
-            if (j.cancel)
-                finish(S, j, ASEP_E_CANCELLED);
-            else if (rcs[i] != ASEP_OK)
-                finish(S, j, rcs[i]);
-            else if (asep_time(j.sim) >= j.t_max && j.next_time >= j.times.size())
+        for (auto& jp : S->active) {
+            Job& j = *jp;
+            int rc = ASEP_OK;
+            if (j.inflight) {
+                const hipError_t q = hipEventQuery(j.done_ev);
+                if (q == hipErrorNotReady) {
+                    still.push_back(jp);
+                    continue;
+                }
+                if (q != hipSuccess) rc = device_error(q, "request event");
+                if (rc == ASEP_OK) collect_quantum(j);
+                progressed = true;
+            }
+            if (rc == ASEP_OK && j.cancel) rc = ASEP_E_CANCELLED;
+            if (rc == ASEP_OK && finished(j)) {
                 finish(S, j, ASEP_OK);
-            else
-                still.push_back(round[i]);
+                continue;
+            }
+            if (rc == ASEP_OK) rc = queue_quantum(S, j);
+            if (rc) {
+                (void)hipStreamSynchronize(j.stream);
+                finish(S, j, rc);
+                continue;
+            }
+            progressed = true;
+            still.push_back(jp);
         }
         S->active.swap(still);
-        S->cv_done.notify_all();
+        if (progressed) S->cv_done.notify_all();
+        if (S->active.empty() && S->queue.empty()) {
+            S->cv_work.wait_for(lk, std::chrono::milliseconds(20));
+        } else if (!progressed) {
+            lk.unlock();
+            std::this_thread::sleep_for(std::chrono::microseconds(50));
+            lk.lock();
+        }
     }
-    // shutdown: release everything still held
+    // shutdown: wait for work in flight, release everything
+    for (uint32_t i = 0; i < kStreams; ++i)
+        if (S->streams[i]) (void)hipStreamSynchronize(S->streams[i]);
     for (auto& j : S->active) finish(S, *j, ASEP_E_CANCELLED);
     S->active.clear();
-    for (auto& j : S->queue) finish(S, *j, ASEP_E_CANCELLED);
+    for (auto& j : S->queue) finish(S, *j, S->init_rc ? S->init_rc : ASEP_E_CANCELLED);
     S->queue.clear();
+    S->arena.release();
+    for (uint32_t i = 0; i < kStreams; ++i)
+        if (S->streams[i]) (void)hipStreamDestroy(S->streams[i]);
     S->cv_done.notify_all();
 }
 
@@ -248,7 +370,7 @@ extern "C" int asep_server_create(const asep_server_cfg* cfg, asep_server** out)
     if (!S->cfg.max_queue) S->cfg.max_queue = 1024;
     if (!S->cfg.max_active) S->cfg.max_active = 64;
     if (!S->cfg.quantum_mcs) S->cfg.quantum_mcs = 1000;
-    if (!S->cfg.hbm_budget_bytes) S->cfg.hbm_budget_bytes = (uint64_t)64 << 30;
+    if (!S->cfg.hbm_budget_bytes) S->cfg.hbm_budget_bytes = (uint64_t)8 << 30;
     try {
         S->worker = std::thread(worker_main, S);
     } catch (...) {
@@ -283,10 +405,12 @@ extern "C" int asep_submit(asep_server* S, const asep_request* req, uint64_t* ti
     j->params = req->params;
     j->t_max = req->t_max;
     j->times.assign(req->times, req->times + req->n_times);
-    j->footprint = sb + ab;
+    j->state_bytes = sb;
+    j->aux_bytes = ab;
     j->t_arrive = now_ns();
     {
         std::lock_guard<std::mutex> lk(S->mu);
+        if (S->init_rc) return S->init_rc;
         if (S->queue.size() >= S->cfg.max_queue) return ASEP_E_BUSY;
         j->ticket = S->next_ticket++;
         S->queue.push_back(j);

@@ -234,3 +234,77 @@ def ensemble_w2(rough_list, L: int) -> float:
     out = ctypes.c_double()
     B.check(B.load().asep_ensemble_w2(arr, n, L, ctypes.byref(out)), "asep_ensemble_w2")
     return out.value
+
+
+class Server:
+    """The request loop (asep_server_*): submit ensemble runs, collect results."""
+
+    def __init__(self, *, device: int = 0, hbm_budget_bytes: int = 8 << 30, max_queue: int = 1024,
+                 max_active: int = 64, quantum_mcs: int = 1000):
+        cfg = B.asep_server_cfg()
+        cfg.abi_version = B.ASEP_ABI_VERSION
+        cfg.device = device
+        cfg.hbm_budget_bytes = hbm_budget_bytes
+        cfg.max_queue = max_queue
+        cfg.max_active = max_active
+        cfg.quantum_mcs = quantum_mcs
+        self._h = ctypes.c_void_p()
+        B.check(B.load().asep_server_create(ctypes.byref(cfg), ctypes.byref(self._h)),
+                "asep_server_create")
+
+    def submit(self, params: B.asep_params, times, t_max: int) -> int:
+        times = [int(t) for t in times]
+        tarr = (ctypes.c_uint64 * max(len(times), 1))(*times)
+        req = B.asep_request()
+        req.params = params
+        req.t_max = int(t_max)
+        req.times = ctypes.cast(tarr, ctypes.POINTER(ctypes.c_uint64))
+        req.n_times = len(times)
+        ticket = ctypes.c_uint64()
+        B.check(B.load().asep_submit(self._h, ctypes.byref(req), ctypes.byref(ticket)),
+                "asep_submit")
+        return ticket.value
+
+    def _result(self, res: B.asep_result) -> dict:
+        out = {"status": int(res.status), "samples": int(res.samples),
+               "n_times": int(res.n_times), "arrive_ns": int(res.t_arrive_ns),
+               "admit_ns": int(res.t_admit_ns), "start_ns": int(res.t_start_ns),
+               "done_ns": int(res.t_done_ns), "site_updates": int(res.site_updates),
+               "rough": []}
+        if res.status == B.ASEP_OK and res.n_times:
+            n, R = res.n_times, res.samples
+            for i in range(n):
+                sub = (B.asep_rough * R).from_address(
+                    ctypes.addressof(res.rough.contents) + i * R * ctypes.sizeof(B.asep_rough))
+                out["rough"].append(_rough_arrays(sub, R))
+            out["times"] = [int(res.times[i]) for i in range(n)]
+        B.load().asep_result_free(ctypes.byref(res))
+        return out
+
+    def poll(self, ticket: int):
+        res = B.asep_result()
+        rc = B.load().asep_poll(self._h, ticket, ctypes.byref(res))
+        if rc == B.ASEP_E_PENDING:
+            return None
+        B.check(rc, "asep_poll")
+        return self._result(res)
+
+    def wait(self, ticket: int, timeout_s: float = 600.0) -> dict:
+        res = B.asep_result()
+        B.check(B.load().asep_wait(self._h, ticket, int(timeout_s * 1e9), ctypes.byref(res)),
+                "asep_wait")
+        return self._result(res)
+
+    def cancel(self, ticket: int) -> None:
+        B.check(B.load().asep_cancel(self._h, ticket), "asep_cancel")
+
+    def close(self) -> None:
+        if self._h:
+            B.load().asep_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

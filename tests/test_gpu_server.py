@@ -1,0 +1,111 @@
+"""The request loop on the GPU: continuous batching changes no result.
+
+Every request's records equal those of the same request run alone through
+asep_run, bit for bit (and the oracle's for the small ones); cancellation,
+back-pressure and the memory budget behave as documented."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+import paper_1012_0385_amd as A  # noqa: E402
+from paper_1012_0385_amd import binding as B  # noqa: E402
+from paper_1012_0385_amd import workloads as W  # noqa: E402
+
+
+def alone(kw, samples, times):
+    sim = A.Simulation(A.make_params(samples=samples, **kw))
+    out = sim.run(times)
+    sim.close()
+    return out
+
+
+def same(a, b):
+    return (np.array_equal(a.S1, b.S1) and a.S2 == b.S2 and np.array_equal(a.J, b.J)
+            and np.array_equal(a.N, b.N))
+
+
+def test_mix_equals_alone(orc):
+    reqs = W.served_mix(24, rate_per_s=1e9, seed=11, max_attempts=2.0**31,
+                        log2_L=(7, 22), log10_t=(1, 2.5), log2_samples=(0, 5))
+    srv = A.Server(quantum_mcs=7, max_active=16)
+    tickets = []
+    for r in reqs:
+        print("submit", r.model, r.L, r.samples, r.t_max, flush=True)
+        tickets.append(srv.submit(A.make_params(samples=r.samples, **r.kwargs()), r.times, r.t_max))
+    for r, t in zip(reqs, tickets):
+        res = srv.wait(t, timeout_s=120)
+        assert res["status"] == 0
+        ref = alone(r.kwargs(), r.samples, r.times)
+        assert len(ref) == len(res["rough"])
+        for x, y in zip(res["rough"], ref):
+            assert same(x, y), (r.model, r.L, r.samples)
+        assert res["site_updates"] == r.attempts
+        assert res["arrive_ns"] <= res["admit_ns"] <= res["start_ns"] <= res["done_ns"]
+    srv.close()
+
+
+def test_server_matches_oracle_small(orc):
+    kw = dict(L=4096, p=1.0, q=0.0, seed=1, stream=1)
+    times = [0, 1, 2, 4, 8, 16, 33]
+    srv = A.Server(quantum_mcs=5)
+    t = srv.submit(A.make_params(samples=4, **kw), times, 40)
+    res = srv.wait(t)
+    P = orc.Params(L=4096, p=1.0, q=0.0, seed=1, stream=1)
+    for i in range(4):
+        ref = orc.run(P, i, times)
+        for ti in range(len(times)):
+            assert res["rough"][ti].S1[i] == ref.S1[ti] and res["rough"][ti].S2[i] == ref.S2[ti]
+            assert res["rough"][ti].J[i] == ref.J[ti]
+    srv.close()
+
+
+def test_cancel_and_unknown_ticket():
+    srv = A.Server(quantum_mcs=10, max_active=1)
+    big = A.make_params(L=1 << 16, samples=64, p=1.0, q=0.0)
+    t1 = srv.submit(big, [0, 100000], 100000)
+    t2 = srv.submit(big, [0, 10], 10)  # queued behind t1
+    srv.cancel(t2)
+    srv.cancel(t1)
+    assert srv.wait(t1)["status"] == B.ASEP_E_CANCELLED
+    assert srv.wait(t2)["status"] == B.ASEP_E_CANCELLED
+    with pytest.raises(A.AsepError):
+        srv.poll(999999)
+    srv.close()
+
+
+def test_queue_full_and_budget():
+    srv = A.Server(max_queue=2, max_active=1, quantum_mcs=10, hbm_budget_bytes=1 << 22)
+    small = A.make_params(L=4096, samples=1)
+    t1 = srv.submit(small, [0, 50], 50)
+    # a request larger than the whole budget can never be admitted
+    huge = A.make_params(L=1 << 20, samples=64)
+    t2 = srv.submit(huge, [0], 0)
+    codes = []
+    for _ in range(6):
+        try:
+            srv.submit(small, [0], 0)
+        except A.AsepError as e:
+            codes.append(e.code)
+    assert B.ASEP_E_BUSY in codes
+    assert srv.wait(t1)["status"] == 0
+    assert srv.wait(t2)["status"] == B.ASEP_E_NOMEM
+    srv.close()
+
+
+def test_invalid_request_rejected():
+    srv = A.Server()
+    with pytest.raises(A.AsepError):
+        srv.submit(A.make_params(L=4096, samples=1), [5, 3], 10)  # unsorted times
+    with pytest.raises(A.AsepError):
+        srv.submit(A.make_params(L=4096, samples=1), [0, 20], 10)  # time past t_max
+    srv.close()
