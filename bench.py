@@ -72,6 +72,75 @@ def cpu_baseline(times_all, n_rings, t_cut):
                       "with the same measurement times; %.1f s wall" % (len(jobs), n_rings, t_cut, dt)}
 
 
+def served_mix_leg(A, W, n_req, load, seed=5):
+    """The served-mix workload: a Poisson stream of ensemble requests with
+    L = 64 ceil(2^x/64), x ~ U[10,26], models KPZ / EW / disorder, t_max =
+    10^U[3,5], samples = 2^U[0,8], redrawn above 2^38 attempts.
+
+    capacity: every request available at t = 0, served (continuous batching)
+    vs plain (one request after another, each one run per launch sequence).
+    latency: arrivals at `load` x the plain capacity; served measured live,
+    plain replayed as a FIFO queue from its measured service times."""
+    import numpy as np
+    import torch
+
+    probe = W.served_mix(n_req, 1.0, seed=seed)
+    total = sum(r.attempts for r in probe)
+
+    # plain capacity: one request at a time
+    service = []
+    t0 = time.perf_counter()
+    for r in probe:
+        ts = time.perf_counter()
+        sim = A.Simulation(A.make_params(samples=r.samples, **r.kwargs()), buffers="library")
+        sim.run(r.times)
+        sim.close()
+        service.append(time.perf_counter() - ts)
+    t_plain = time.perf_counter() - t0
+
+    def serve(reqs, live_arrivals):
+        srv = A.Server(quantum_mcs=2000, max_active=64)
+        tickets = []
+        start = time.perf_counter()
+        for r in reqs:
+            if live_arrivals:
+                delay = r.arrival_s - (time.perf_counter() - start)
+                if delay > 0:
+                    time.sleep(delay)
+            tickets.append(srv.submit(A.make_params(samples=r.samples, **r.kwargs()), r.times,
+                                      r.t_max))
+        res = [srv.wait(t, timeout_s=600) for t in tickets]
+        srv.close()
+        assert all(x["status"] == 0 for x in res)
+        lat = [(x["done_ns"] - x["arrive_ns"]) * 1e-9 for x in res]
+        span = (max(x["done_ns"] for x in res) - min(x["arrive_ns"] for x in res)) * 1e-9
+        return lat, span
+
+    torch.cuda.synchronize()
+    _, t_served = serve(probe, live_arrivals=False)
+    cap_plain = total / t_plain
+    cap_served = total / t_served
+    # Poisson arrivals at `load` x the plain capacity
+    rate = load * cap_plain / (total / n_req)
+    reqs = W.served_mix(n_req, rate, seed=seed)
+    lat_s, span_s = serve(reqs, live_arrivals=True)
+    done, lat_p = 0.0, []
+    for r, svc in zip(reqs, service):
+        done = max(done, r.arrival_s) + svc
+        lat_p.append(done - r.arrival_s)
+    pct = lambda v, q: float(np.percentile(np.array(v), q))
+    return {
+        "workload": "served mix: %d Poisson requests, L=64*ceil(2^U[10,26]/64), KPZ/EW/disorder, "
+                    "t_max=10^U[3,5], samples=2^U[0,8], capped at 2^38 attempts" % n_req,
+        "site_updates": total,
+        "capacity": {"served": cap_served, "plain": cap_plain, "unit": "site-updates/s"},
+        "load": load, "arrival_rate_per_s": rate,
+        "latency_s": {"served": {"p50": pct(lat_s, 50), "p99": pct(lat_s, 99)},
+                      "plain": {"p50": pct(lat_p, 50), "p99": pct(lat_p, 99)}},
+        "served_throughput_at_load": total / span_s,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -81,6 +150,8 @@ def main():
     ap.add_argument("--cpu-rings", type=int, default=16)
     ap.add_argument("--cpu-mcs", type=int, default=1000)
     ap.add_argument("--t-max", type=int, default=T_MAX)
+    ap.add_argument("--mix-requests", type=int, default=48, help="served-mix requests (0: skip)")
+    ap.add_argument("--mix-load", type=float, default=0.8)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -149,6 +220,13 @@ def main():
                 "unit": "TOP/s", "frac": achieved / PEAK_SLOTS, "traffic": None,
                 "kernel": "k_sweep", "avg_launch_ms": avg_ms, "launches": launches}
 
+    mix = None
+    if args.mix_requests > 0:
+        from paper_1012_0385_amd import workloads as W
+
+        mix = served_mix_leg(A, W, args.mix_requests, args.mix_load)
+        print("served mix: %s" % json.dumps(mix), file=sys.stderr)
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(times, args.cpu_rings, args.cpu_mcs)
@@ -173,6 +251,7 @@ def main():
                    "measurements": len(times), "parallelism": "1 GPU"},
         "plain": {"value": plain_value, "ms_per_step": t_plain / args.steps * 1e3},
         "roofline": roofline,
+        "served_mix": mix,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -364,7 +364,7 @@ __host__ __device__ constexpr uint32_t sweep_max_block(int C, int model = kPlain
 // starting at sig + 64*(base + off + i) (mod L).
 // ---------------------------------------------------------------------------
 template <int C, int MODEL, int V, bool Q0>
-__global__ __launch_bounds__(sweep_max_block(C, MODEL)) void k_sweep(const SimDesc P) {
+__device__ __forceinline__ void sweep_body(const SimDesc& P) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int NPL = (MODEL == kTwoLane) ? 2 : 1;
     constexpr bool FAST = V != kGeneric;
@@ -680,50 +680,83 @@ __global__ __launch_bounds__(sweep_max_block(C, MODEL)) void k_sweep(const SimDe
     }
 }
 
+// Workgroup -> simulation of a packed launch (descriptors sorted by wg_begin).
+__device__ __forceinline__ uint32_t find_desc(const SimDesc* __restrict__ d, uint32_t n,
+                                              uint32_t wg) {
+    uint32_t lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (d[mid].wg_begin <= wg)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// One simulation per launch: the descriptor travels in the kernel arguments.
+template <int C, int MODEL, int V, bool Q0>
+__global__ __launch_bounds__(sweep_max_block(C, MODEL)) void k_sweep(const SimDesc P) {
+    sweep_body<C, MODEL, V, Q0>(P);
+}
+
+// Packed launch: workgroups of several simulations (requests) in one grid,
+// each finding its descriptor in device memory.
+template <int C, int MODEL, int V, bool Q0>
+__global__ __launch_bounds__(sweep_max_block(C, MODEL)) void k_sweep_packed(
+    const SimDesc* __restrict__ descs, uint32_t n_desc) {
+    sweep_body<C, MODEL, V, Q0>(descs[find_desc(descs, n_desc, blockIdx.x)]);
+}
+
 // Dispatch of one model's kernels over (C, variant, q0).  Compiled variants:
 // generic for every C; fast (ell = 64) for C <= 8 -- single lane with 5, 4 or
 // 1 fields per word, each with and without backward hops; two lanes with 4 or
 // 1 fields per word.
+// Packed launches are compiled for the small-ring shapes (C <= 4).
 template <int MODEL, int C, int V, bool Q>
 inline void launch_one(const SimDesc& one, const SimDesc* descs, uint32_t n_desc, uint32_t grid,
                        uint32_t block, size_t lds, hipStream_t st) {
-    (void)descs;
-    (void)n_desc;
+    if constexpr (C <= 4) {
+        if (descs) {
+            hipLaunchKernelGGL((k_sweep_packed<C, MODEL, V, Q>), dim3(grid), dim3(block), lds, st,
+                               descs, n_desc);
+            return;
+        }
+    }
     hipLaunchKernelGGL((k_sweep<C, MODEL, V, Q>), dim3(grid), dim3(block), lds, st, one);
 }
 
 template <int MODEL, int C, int V>
-inline void launch_q(const SweepKernel& k, const SimDesc& one, uint32_t grid, uint32_t block,
-                     size_t lds, hipStream_t st) {
+inline void launch_q(const SweepKernel& k, const SimDesc& one, const SimDesc* descs,
+                     uint32_t n_desc, uint32_t grid, uint32_t block, size_t lds, hipStream_t st) {
     if (MODEL != kTwoLane && k.q0)
-        launch_one<MODEL, C, V, true>(one, nullptr, 0, grid, block, lds, st);
+        launch_one<MODEL, C, V, true>(one, descs, n_desc, grid, block, lds, st);
     else
-        launch_one<MODEL, C, V, false>(one, nullptr, 0, grid, block, lds, st);
+        launch_one<MODEL, C, V, false>(one, descs, n_desc, grid, block, lds, st);
 }
 
 template <int MODEL, int C>
 inline hipError_t launch_c(const SweepKernel& k, const SimDesc& one, const SimDesc* descs,
                            uint32_t n_desc, uint32_t grid, uint32_t block, size_t lds,
                            hipStream_t st) {
-    (void)descs;
-    (void)n_desc;
+    if (descs && C > 4) return hipErrorInvalidValue;
     if (k.variant == kGeneric) {
-        launch_one<MODEL, C, kGeneric, false>(one, nullptr, 0, grid, block, lds, st);
+        launch_one<MODEL, C, kGeneric, false>(one, descs, n_desc, grid, block, lds, st);
         return hipSuccess;
     }
     if constexpr (C <= 8) {
         if constexpr (MODEL == kTwoLane) {
             switch (k.variant) {
-                case kF4B0: launch_one<MODEL, C, kF4B0, false>(one, nullptr, 0, grid, block, lds, st); return hipSuccess;
-                case kF1: launch_one<MODEL, C, kF1, false>(one, nullptr, 0, grid, block, lds, st); return hipSuccess;
+                case kF4B0: launch_one<MODEL, C, kF4B0, false>(one, descs, n_desc, grid, block, lds, st); return hipSuccess;
+                case kF1: launch_one<MODEL, C, kF1, false>(one, descs, n_desc, grid, block, lds, st); return hipSuccess;
                 default: return hipErrorInvalidValue;
             }
         } else {
             switch (k.variant) {
-                case kF5B0: launch_q<MODEL, C, kF5B0>(k, one, grid, block, lds, st); return hipSuccess;
-                case kF4B1: launch_q<MODEL, C, kF4B1>(k, one, grid, block, lds, st); return hipSuccess;
-                case kF4B2: launch_q<MODEL, C, kF4B2>(k, one, grid, block, lds, st); return hipSuccess;
-                case kF1: launch_q<MODEL, C, kF1>(k, one, grid, block, lds, st); return hipSuccess;
+                case kF5B0: launch_q<MODEL, C, kF5B0>(k, one, descs, n_desc, grid, block, lds, st); return hipSuccess;
+                case kF4B1: launch_q<MODEL, C, kF4B1>(k, one, descs, n_desc, grid, block, lds, st); return hipSuccess;
+                case kF4B2: launch_q<MODEL, C, kF4B2>(k, one, descs, n_desc, grid, block, lds, st); return hipSuccess;
+                case kF1: launch_q<MODEL, C, kF1>(k, one, descs, n_desc, grid, block, lds, st); return hipSuccess;
                 default: return hipErrorInvalidValue;
             }
         }

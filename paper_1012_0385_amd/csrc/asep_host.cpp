@@ -737,6 +737,41 @@ int sim_run_async(asep_sim* s, const uint64_t* times, uint32_t n, uint64_t t_end
 
 void record_to_rough(const asep_sim* s, const Record& rc, asep_rough* o) { fill_rough(s->r, rc, o); }
 
+// Packing: whole-ring simulations of the small shapes can share a launch
+// with other simulations of the same kernel and workgroup size.
+bool sim_pack_info(const asep_sim* s, PackInfo* pi) {
+    const Plan& pl = s->plan;
+    pi->kern = pl.kern;
+    pi->block = pl.block;
+    pi->lds = pl.lds;
+    pi->grid = pl.grid;
+    return !pl.seg && pl.kern.C <= 4;
+}
+
+// Descriptor advancing the simulation to t_end with measurements at
+// times[0..n) (n <= the record capacity); wg_begin is left to the caller.
+int sim_pack_prepare(asep_sim* s, uint64_t t_end, const uint64_t* times, uint32_t n,
+                     SimDesc* d) {
+    if (s->plan.seg || n > s->rec_cap || t_end < s->t) return ASEP_E_INVAL;
+    const uint32_t S = s->r.sc.S;
+    *d = make_desc(s);
+    for (uint32_t i = 0; i < n; ++i) d->rec_g[i] = times[i] * S;
+    d->g0 = s->t * S;
+    d->g1 = t_end * S;
+    d->n_rec = n;
+    return ASEP_OK;
+}
+
+// After the packed launch: the clock moves to t_end and the records are
+// copied to host_out on the launch's stream.
+int sim_pack_commit(asep_sim* s, uint64_t t_end, uint32_t n, Record* host_out, hipStream_t st) {
+    s->t = t_end;
+    if (n && host_out)
+        HIP_OR_FAIL(hipMemcpyAsync(host_out, s->rec, sizeof(Record) * n * s->r.P.samples,
+                                   hipMemcpyDeviceToHost, st));
+    return ASEP_OK;
+}
+
 int device_error(hipError_t e, const char* where) { return device_fail(e, where); }
 
 }  // namespace asep

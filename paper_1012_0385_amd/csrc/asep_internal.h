@@ -112,5 +112,14 @@ uint64_t sim_attempts_per_mcs(const asep_sim* s);
 int sim_run_async(asep_sim* s, const uint64_t* times_pinned, uint32_t n, uint64_t t_end,
                   Record* host_out);
 void record_to_rough(const asep_sim* s, const Record& rc, asep_rough* o);
+struct PackInfo {
+    SweepKernel kern;
+    uint32_t block, grid;
+    size_t lds;
+};
+bool sim_pack_info(const asep_sim* s, PackInfo* pi);
+int sim_pack_prepare(asep_sim* s, uint64_t t_end, const uint64_t* times, uint32_t n,
+                     SimDesc* d);
+int sim_pack_commit(asep_sim* s, uint64_t t_end, uint32_t n, Record* host_out, hipStream_t st);
 int device_error(hipError_t e, const char* where);
 }  // namespace asep

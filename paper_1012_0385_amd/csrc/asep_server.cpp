@@ -27,6 +27,7 @@
 #include <mutex>
 #include <new>
 #include <thread>
+#include <tuple>
 #include <vector>
 
 #include "../../include/asep.h"
@@ -143,6 +144,12 @@ struct asep_server {
     Arena arena;
     hipStream_t streams[kStreams] = {};
     uint32_t next_stream = 0;
+    // packed launches: one descriptor buffer per stream
+    SimDesc* pack_host[kStreams] = {};
+    SimDesc* pack_dev[kStreams] = {};
+    hipEvent_t pack_ev[kStreams] = {};
+    bool pack_used[kStreams] = {};
+    uint64_t packed_launches = 0;
     int init_rc = ASEP_OK;
 };
 
@@ -202,8 +209,8 @@ int admit(asep_server* S, Job& j) {
     return ASEP_OK;
 }
 
-// Queue the job's next quantum and record its event.
-int queue_quantum(asep_server* S, Job& j) {
+// The job's next quantum: end time and number of measurements in it.
+void next_quantum(asep_server* S, const Job& j, uint64_t* t_end_out, uint32_t* n_out) {
     const uint64_t t = asep_time(j.sim);
     const uint64_t q = std::max<uint64_t>(S->cfg.quantum_mcs, 1);
     uint64_t t_end = std::min(j.t_max, t + q);
@@ -212,16 +219,80 @@ int queue_quantum(asep_server* S, Job& j) {
     while (j.next_time + n < j.times.size() && j.times[j.next_time + n] <= t_end && n < cap) ++n;
     if (n == cap && j.next_time + n < j.times.size() && j.times[j.next_time + n] <= t_end)
         t_end = j.times[j.next_time + n - 1];
+    *t_end_out = t_end;
+    *n_out = n;
+}
+
+void mark_queued(Job& j, uint64_t t0, uint64_t t_end, uint32_t n) {
     if (!j.t_start) j.t_start = now_ns();
-    int rc = sim_run_async(j.sim, j.times.data() + j.next_time, n, t_end, j.pinned_rec);
-    if (rc) return rc;
-    if (hipEventRecord(j.done_ev, j.stream) != hipSuccess) return ASEP_E_DEVICE;
-    j.updates += (t_end - t) * sim_attempts_per_mcs(j.sim);
+    j.updates += (t_end - t0) * sim_attempts_per_mcs(j.sim);
     j.staged_first = j.next_time;
     j.staged_n = n;
     j.next_time += n;
     j.inflight = true;
+}
+
+// Queue the job's next quantum on its own stream and record its event.
+int queue_quantum(asep_server* S, Job& j) {
+    uint64_t t_end;
+    uint32_t n;
+    next_quantum(S, j, &t_end, &n);
+    const uint64_t t0 = asep_time(j.sim);
+    if (!j.t_start) j.t_start = now_ns();
+    int rc = sim_run_async(j.sim, j.times.data() + j.next_time, n, t_end, j.pinned_rec);
+    if (rc) return rc;
+    if (hipEventRecord(j.done_ev, j.stream) != hipSuccess) return ASEP_E_DEVICE;
+    mark_queued(j, t0, t_end, n);
     return ASEP_OK;
+}
+
+// Queue the next quanta of several jobs with the same kernel shape as one
+// launch on a free stream of the pool.  Returns false if no stream is free.
+bool queue_packed(asep_server* S, const std::vector<Job*>& group, const PackInfo& pi,
+                  std::vector<int>* rcs) {
+    uint32_t slot = kStreams;
+    for (uint32_t k = 0; k < kStreams; ++k) {
+        if (!S->pack_used[k] || hipEventQuery(S->pack_ev[k]) == hipSuccess) {
+            slot = k;
+            break;
+        }
+    }
+    if (slot == kStreams) return false;
+    hipStream_t st = S->streams[slot];
+    SimDesc* hd = S->pack_host[slot];
+    std::vector<uint64_t> t_end(group.size()), t0(group.size());
+    std::vector<uint32_t> n(group.size());
+    uint32_t wg = 0;
+    size_t lds = 0;
+    for (size_t i = 0; i < group.size(); ++i) {
+        Job& j = *group[i];
+        next_quantum(S, j, &t_end[i], &n[i]);
+        t0[i] = asep_time(j.sim);
+        (*rcs)[i] = sim_pack_prepare(j.sim, t_end[i], j.times.data() + j.next_time, n[i], &hd[i]);
+        PackInfo ji;
+        sim_pack_info(j.sim, &ji);
+        hd[i].wg_begin = wg;
+        wg += ji.grid;
+        lds = std::max(lds, ji.lds);
+    }
+    for (int rc : *rcs)
+        if (rc) return true;  // reported per job by the caller
+    const uint32_t nd = (uint32_t)group.size();
+    hipError_t e = hipMemcpyAsync(S->pack_dev[slot], hd, sizeof(SimDesc) * nd,
+                                  hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = launch_sweep(pi.kern, hd[0], S->pack_dev[slot], nd, wg, pi.block, lds, st);
+    for (size_t i = 0; i < group.size(); ++i) {
+        Job& j = *group[i];
+        int rc = (e == hipSuccess) ? ASEP_OK : device_error(e, "packed launch");
+        if (rc == ASEP_OK) rc = sim_pack_commit(j.sim, t_end[i], n[i], j.pinned_rec, st);
+        if (rc == ASEP_OK && hipEventRecord(j.done_ev, st) != hipSuccess) rc = ASEP_E_DEVICE;
+        if (rc == ASEP_OK) mark_queued(j, t0[i], t_end[i], n[i]);
+        (*rcs)[i] = rc;
+    }
+    (void)hipEventRecord(S->pack_ev[slot], st);
+    S->pack_used[slot] = true;
+    S->packed_launches += 1;
+    return true;
 }
 
 void collect_quantum(Job& j) {
@@ -248,6 +319,13 @@ void worker_main(asep_server* S) {
         if (hipStreamCreateWithFlags(&S->streams[i], hipStreamNonBlocking) != hipSuccess)
             S->init_rc = ASEP_E_DEVICE;
     if (S->init_rc == ASEP_OK && !S->arena.init(S->cfg.hbm_budget_bytes)) S->init_rc = ASEP_E_NOMEM;
+    for (uint32_t i = 0; i < kStreams && S->init_rc == ASEP_OK; ++i) {
+        const size_t bytes = sizeof(SimDesc) * S->cfg.max_active;
+        if (hipHostMalloc((void**)&S->pack_host[i], bytes) != hipSuccess ||
+            hipMalloc((void**)&S->pack_dev[i], bytes) != hipSuccess ||
+            hipEventCreateWithFlags(&S->pack_ev[i], hipEventDisableTiming) != hipSuccess)
+            S->init_rc = ASEP_E_NOMEM;
+    }
     {
         std::lock_guard<std::mutex> lk(S->mu);
         S->cv_done.notify_all();
@@ -282,8 +360,10 @@ void worker_main(asep_server* S) {
             S->active.push_back(j);
             progressed = true;
         }
-        // progress: every request whose quantum is done gets its next one
+        // progress: every request whose quantum is done gets its next one;
+        // ready requests of the same small-ring kernel shape share a launch
         std::vector<std::shared_ptr<Job>> still;
+        std::vector<Job*> ready;
         for (auto& jp : S->active) {
             Job& j = *jp;
             int rc = ASEP_OK;
@@ -302,14 +382,60 @@ void worker_main(asep_server* S) {
                 finish(S, j, ASEP_OK);
                 continue;
             }
-            if (rc == ASEP_OK) rc = queue_quantum(S, j);
             if (rc) {
                 (void)hipStreamSynchronize(j.stream);
                 finish(S, j, rc);
                 continue;
             }
-            progressed = true;
+            ready.push_back(&j);
             still.push_back(jp);
+        }
+        // group the ready jobs by kernel shape
+        std::map<std::tuple<uint32_t, uint32_t, uint32_t, bool, uint32_t>, std::vector<Job*>> groups;
+        std::vector<Job*> single;
+        for (Job* j : ready) {
+            PackInfo pi;
+            if (sim_pack_info(j->sim, &pi))
+                groups[std::make_tuple(pi.kern.C, pi.kern.model, pi.kern.variant, pi.kern.q0,
+                                       pi.block)]
+                    .push_back(j);
+            else
+                single.push_back(j);
+        }
+        std::vector<std::pair<Job*, int>> failed;
+        for (auto& kv : groups) {
+            auto& g = kv.second;
+            if (g.size() >= 2) {
+                PackInfo pi;
+                sim_pack_info(g[0]->sim, &pi);
+                std::vector<int> rcs(g.size(), ASEP_OK);
+                if (queue_packed(S, g, pi, &rcs)) {
+                    for (size_t i = 0; i < g.size(); ++i)
+                        if (rcs[i]) failed.push_back({g[i], rcs[i]});
+                    progressed = true;
+                    continue;
+                }
+            }
+            for (Job* j : g) single.push_back(j);
+        }
+        for (Job* j : single) {
+            int rc = queue_quantum(S, *j);
+            if (rc) failed.push_back({j, rc});
+            progressed = true;
+        }
+        if (!failed.empty()) {
+            std::vector<std::shared_ptr<Job>> keep;
+            for (auto& jp : still) {
+                auto it = std::find_if(failed.begin(), failed.end(),
+                                       [&](const std::pair<Job*, int>& f) { return f.first == jp.get(); });
+                if (it == failed.end()) {
+                    keep.push_back(jp);
+                    continue;
+                }
+                for (uint32_t k = 0; k < kStreams; ++k) (void)hipStreamSynchronize(S->streams[k]);
+                finish(S, *jp, it->second);
+            }
+            still.swap(keep);
         }
         S->active.swap(still);
         if (progressed) S->cv_done.notify_all();
@@ -329,8 +455,12 @@ void worker_main(asep_server* S) {
     for (auto& j : S->queue) finish(S, *j, S->init_rc ? S->init_rc : ASEP_E_CANCELLED);
     S->queue.clear();
     S->arena.release();
-    for (uint32_t i = 0; i < kStreams; ++i)
+    for (uint32_t i = 0; i < kStreams; ++i) {
+        if (S->pack_host[i]) (void)hipHostFree(S->pack_host[i]);
+        if (S->pack_dev[i]) (void)hipFree(S->pack_dev[i]);
+        if (S->pack_ev[i]) (void)hipEventDestroy(S->pack_ev[i]);
         if (S->streams[i]) (void)hipStreamDestroy(S->streams[i]);
+    }
     S->cv_done.notify_all();
 }
 

@@ -54,6 +54,25 @@ def test_mix_equals_alone(orc):
     srv.close()
 
 
+def test_packed_small_requests_equal_alone():
+    # many small rings of one kernel shape: they share launches in the server
+    reqs = []
+    for i in range(20):
+        kw = dict(L=1024 + 64 * (i % 3), p=[1.0, 0.5, 0.75][i % 3], q=[0.0, 0.5, 0.25][i % 3],
+                  seed=7 + i, stream=i)
+        if i % 5 == 4:
+            kw.update(slow_frac=0.2, slow_factor=0.5)
+        reqs.append((kw, 1 + i % 4, [0, 3, 17, 40 + i]))
+    srv = A.Server(quantum_mcs=11, max_active=32)
+    tickets = [srv.submit(A.make_params(samples=n, **kw), times, times[-1]) for kw, n, times in reqs]
+    for (kw, n, times), t in zip(reqs, tickets):
+        res = srv.wait(t, timeout_s=120)
+        assert res["status"] == 0
+        for x, y in zip(res["rough"], alone(kw, n, times)):
+            assert same(x, y), kw
+    srv.close()
+
+
 def test_server_matches_oracle_small(orc):
     kw = dict(L=4096, p=1.0, q=0.0, seed=1, stream=1)
     times = [0, 1, 2, 4, 8, 16, 33]
