@@ -15,7 +15,8 @@ the batched form.
 
 The JSON line also carries the ALU roofline of the dominant kernel (the
 sweep kernel: per-launch algorithmic instruction slots over its average
-duration from HIP events on its own stream) and the CPU oracle timed on
+duration from HIP events on its own stream, taken in the plain form so that
+no two launches overlap) and the CPU oracle timed on
 the host cores over a bounded prefix of the same workload.
 """
 import argparse
@@ -152,6 +153,8 @@ def main():
     ap.add_argument("--t-max", type=int, default=T_MAX)
     ap.add_argument("--mix-requests", type=int, default=48, help="served-mix requests (0: skip)")
     ap.add_argument("--mix-load", type=float, default=0.8)
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="only run a device-to-device copy of this many MiB (counter scale)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -164,12 +167,27 @@ def main():
     import paper_1012_0385_amd as A
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy_mib:
+        n = args.calibrate_copy_mib << 20
+        src = torch.ones(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n}))
+        return
     times = A.sample_times(30, 1.05, args.t_max)
     if times[-1] != args.t_max:
         times.append(args.t_max)
+    from paper_1012_0385_amd import tune
+
     streams = [torch.cuda.Stream() for _ in MODELS]
-    sims = [A.Simulation(A.make_params(L=L, samples=SAMPLES, p=p, q=q, seed=1, stream=sid),
-                         stream=st) for (name, p, q, sid), st in zip(MODELS, streams)]
+    sims = []
+    shapes = []
+    for (name, p, q, sid), st in zip(MODELS, streams):
+        kw = dict(L=L, p=p, q=q, seed=1, stream=sid)
+        shape = tune.lookup(kw, SAMPLES)  # launch shape only; results do not depend on it
+        shapes.append(shape)
+        sims.append(A.Simulation(A.make_params(samples=SAMPLES, **kw, **shape), stream=st))
     attempts_per_step = sum(s.samples * s.L for s in sims) * args.t_max
 
     def run_one(sim, out, k):
@@ -197,20 +215,22 @@ def main():
 
     for _ in range(args.warmup):
         step_batched()
-    # plain form
-    t_plain = timed(step_plain, args.steps)
-    # batched form, with kernel timing on
+    # plain form, with kernel timing on: launches of one ensemble never
+    # overlap, so each event pair times one kernel alone
     for s in sims:
         s.profile(True)
-    t_batch = timed(step_batched, args.steps)
+    t_plain = timed(step_plain, args.steps)
     prof = [s.profile_read() for s in sims]
     for s in sims:
         s.profile(False)
+    # batched form
+    t_batch = timed(step_batched, args.steps)
     print("plain %.3f s, batched %.3f s over %d steps" % (t_plain, t_batch, args.steps),
           file=sys.stderr)
 
-    value = attempts_per_step * args.steps / t_batch
+    batched_value = attempts_per_step * args.steps / t_batch
     plain_value = attempts_per_step * args.steps / t_plain
+    value = batched_value
     launches = sum(p["launches"] for p in prof)
     kernel_ms = sum(p["kernel_ms"] for p in prof)
     slots = sum(p["attempts"] * alu_slots_per_attempt(s) for p, s in zip(prof, sims))
@@ -248,8 +268,10 @@ def main():
                                "and EW (p=q=0.5), 64 samples each, 10^5 MCS, W^2 at t=0 and "
                                "ceil(30*1.05^i)",
                    "rings": len(sims) * SAMPLES, "L": L, "t_max": args.t_max,
+                   "launch_shape": shapes[0] or "automatic",
                    "measurements": len(times), "parallelism": "1 GPU"},
         "plain": {"value": plain_value, "ms_per_step": t_plain / args.steps * 1e3},
+        "batched": {"value": batched_value, "ms_per_step": t_batch / args.steps * 1e3},
         "roofline": roofline,
         "served_mix": mix,
         "cpu_baseline": cpu,

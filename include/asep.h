@@ -94,7 +94,8 @@ typedef struct asep_params {
                           1 = each ring whole in one workgroup, n >= 2 = each
                           ring cut into n windows (one workgroup each) */
     uint32_t window_sweeps; /* sub-sweeps per launch of a windowed ring; 0 = 63 */
-    uint32_t reserved;
+    uint32_t rings_per_wg;  /* launch shape only: whole rings packed per
+                               workgroup; 0 = automatic */
 } asep_params;
 
 /* Roughness and current of one sample at one time (Sec. 2.1, Eq. W).

@@ -53,7 +53,7 @@ class asep_params(ctypes.Structure):
         ("rbits", ctypes.c_int32),
         ("windows", ctypes.c_uint32),
         ("window_sweeps", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32),
+        ("rings_per_wg", ctypes.c_uint32),
     ]
 
 

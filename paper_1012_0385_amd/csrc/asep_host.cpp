@@ -236,7 +236,11 @@ static bool plan_whole(const Resolved& r, Plan* p) {
         const uint32_t Tr = (nw + C - 1) / C;
         if (Tr > maxb) continue;
         uint32_t G = 1;
-        if (Tr < 256) G = std::max(1u, std::min(256u / Tr, R));
+        if (r.P.rings_per_wg)
+            G = std::min(r.P.rings_per_wg, R);
+        else if (Tr < 256)
+            G = std::max(1u, std::min(256u / Tr, R));
+        if ((uint64_t)G * Tr > maxb) continue;
         const uint32_t block = std::min(maxb, (G * Tr + 63) / 64 * 64);
         if (block < G * Tr) continue;
         const size_t lds = sweep_lds_bytes(block, r.planes, G, r.mplanes, nw);

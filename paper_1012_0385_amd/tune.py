@@ -1,0 +1,140 @@
+"""Autotuner of launch shapes.
+
+For a given set of run parameters it times short probe runs of candidate
+launch shapes -- whole rings with several rings per workgroup, or rings cut
+into windows advanced several sub-sweeps per launch -- and keeps the fastest.
+These knobs never change results (every shape computes the same bits; the GPU
+parity tests check shape invariance), so tuning is free to pick any of them.
+The update rule itself (cell size, sub-sweeps per MCS) is not tuned here: it
+defines the trajectory and stays the caller's choice.
+
+Tables are JSON: {"version": ..., "device": ..., "entries": {key: shape}},
+key = "model:L:samples:cell_log2:subsweeps:rbits", shape = {"windows": w,
+"window_sweeps": k, "rings_per_wg": g, "rate": attempts/s}.
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+
+from . import binding as B
+from .sim import Simulation, make_params, run_batch
+
+TABLE_VERSION = 1
+DEFAULT_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json")
+
+
+def key_of(kw: dict, samples: int) -> str:
+    return "%d:%d:%d:%d:%d:%d" % (kw.get("model", 0), kw["L"], samples, kw.get("cell_log2", 0),
+                                  kw.get("subsweeps", 0), kw.get("rbits", -1))
+
+
+def candidates(L: int, samples: int, n_cu: int = 256):
+    """Launch shapes worth trying for rings of L sites."""
+    nw = L // 64
+    out = [dict(windows=1, window_sweeps=0, rings_per_wg=0)]
+    for w in (2, 3, 4, 6, 8, 16, 32, 64, 128, 256):
+        if nw // w < 64:
+            break
+        for k in (15, 31, 63, 127):
+            if nw // w >= 4 * (k + 1):
+                out.append(dict(windows=w, window_sweeps=k, rings_per_wg=0))
+    if nw <= 64:
+        for g in (1, 2, 4, 8, 16):
+            out.append(dict(windows=1, window_sweeps=0, rings_per_wg=g))
+    return out
+
+
+def _probe(kws, samples, shape, times, streams) -> float:
+    sims = []
+    try:
+        for kw, st in zip(kws, streams):
+            sims.append(Simulation(make_params(samples=samples, **kw, **shape), stream=st))
+    except B.AsepError:
+        for s in sims:
+            s.close()
+        return 0.0
+    import torch
+
+    run_batch(sims, times[:2])  # warm-up launch
+    for s in sims:
+        s.reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run_batch(sims, times)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    work = sum(s.samples * s.L * (4 if s.planes == 2 else 1) for s in sims) * times[-1]
+    for s in sims:
+        s.close()
+    return work / dt
+
+
+def tune(kws, samples: int, times, shapes=None, verbose: bool = False) -> dict:
+    """Fastest launch shape for the simulations `kws` run together (each with
+    `samples` rings) through the measurement times `times`."""
+    import torch
+
+    streams = [torch.cuda.Stream() for _ in kws]
+    shapes = shapes or candidates(kws[0]["L"], samples)
+    best = None
+    for sh in shapes:
+        rate = _probe(kws, samples, sh, times, streams)
+        if verbose:
+            print("tune", sh, "%.3e" % rate, flush=True)
+        if rate > 0 and (best is None or rate > best["rate"]):
+            best = dict(sh, rate=rate)
+    return best
+
+
+def load_table(path: str = DEFAULT_TABLE) -> dict:
+    if not os.path.exists(path):
+        return {"version": TABLE_VERSION, "entries": {}}
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("version") != TABLE_VERSION:
+        return {"version": TABLE_VERSION, "entries": {}}
+    return t
+
+
+def lookup(kw: dict, samples: int, path: str = DEFAULT_TABLE) -> dict:
+    """Tuned shape for (kw, samples), or {} (automatic)."""
+    e = load_table(path)["entries"].get(key_of(kw, samples))
+    if not e:
+        return {}
+    return {k: e[k] for k in ("windows", "window_sweeps", "rings_per_wg")}
+
+
+def store(kw: dict, samples: int, shape: dict, device: str, path: str = DEFAULT_TABLE) -> None:
+    t = load_table(path)
+    t["device"] = device
+    t["entries"][key_of(kw, samples)] = shape
+    with open(path, "w") as f:
+        json.dump(t, f, indent=1, sort_keys=True)
+
+
+if __name__ == "__main__":
+    import argparse
+
+    import torch
+
+    ap = argparse.ArgumentParser(description="tune launch shapes of the benchmark workloads")
+    ap.add_argument("--t-max", type=int, default=2000)
+    ap.add_argument("--out", default=DEFAULT_TABLE)
+    args = ap.parse_args()
+    from .sim import sample_times
+
+    times = sample_times(30, 1.05, args.t_max)
+    if times[-1] != args.t_max:
+        times.append(args.t_max)
+    dev = torch.cuda.get_device_properties(0).gcnArchName
+    jobs = [
+        # the L = 2^17 KPZ + EW pair (run together)
+        ([dict(L=1 << 17, p=1.0, q=0.0, seed=1, stream=0), dict(L=1 << 17, p=0.5, q=0.5, seed=1, stream=1)], 64),
+    ]
+    for kws, samples in jobs:
+        best = tune(kws, samples, times, verbose=True)
+        print("best", best, flush=True)
+        for kw in kws:
+            store(kw, samples, best, dev, args.out)
