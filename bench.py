@@ -142,6 +142,43 @@ def served_mix_leg(A, W, n_req, load, seed=5):
     }
 
 
+def other_workloads(A, t_cut=1000):
+    """Site-updates/s of the other workload shapes (one timed run each after a
+    warm-up; prefixes of the long ones, with their measurement times)."""
+    import torch
+
+    from paper_1012_0385_amd import tune
+
+    out = {}
+    cases = [
+        ("small_L4096", dict(L=4096, p=1.0, q=0.0, seed=1, stream=1), 8,
+         [0] + [2 ** k for k in range(10)] + [1000], "8 rings of 4096 sites, KPZ, 1000 MCS (full)"),
+        ("disorder_L2p16", dict(L=1 << 16, p=1.0, q=0.0, slow_frac=0.1, slow_factor=0.5,
+                                samples_per_disorder=4, seed=1, stream=2), 4096, None,
+         "1024 disorder realisations x 4 noise, L=2^16, first %d of 10^6 MCS" % t_cut),
+        ("two_lane_L2p16", dict(L=1 << 16, model=1, init=1, density=0.3, p=1.0, q=1.0,
+                                lane_rate=0.1, turn_frac=0.05, seed=1, stream=3), 1024, None,
+         "1024 two-lane rings of 2^16 per lane, first %d of 10^5 MCS" % t_cut),
+    ]
+    for name, kw, samples, times, desc in cases:
+        if times is None:
+            times = A.sample_times(30, 1.05, t_cut)
+            if times[-1] != t_cut:
+                times.append(t_cut)
+        sim = A.Simulation(A.make_params(samples=samples, **kw, **tune.lookup(kw, samples)))
+        sim.run(times[:3])
+        sim.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.run(times)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        work = samples * kw["L"] * (4 if kw.get("model", 0) == 1 else 1) * times[-1]
+        out[name] = {"value": work / dt, "unit": "site-updates/s", "seconds": dt, "workload": desc}
+        sim.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -153,6 +190,7 @@ def main():
     ap.add_argument("--t-max", type=int, default=T_MAX)
     ap.add_argument("--mix-requests", type=int, default=48, help="served-mix requests (0: skip)")
     ap.add_argument("--mix-load", type=float, default=0.8)
+    ap.add_argument("--no-others", action="store_true", help="skip the other workload shapes")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a device-to-device copy of this many MiB (counter scale)")
     args = ap.parse_args()
@@ -240,6 +278,10 @@ def main():
                 "unit": "TOP/s", "frac": achieved / PEAK_SLOTS, "traffic": None,
                 "kernel": "k_sweep", "avg_launch_ms": avg_ms, "launches": launches}
 
+    others = None if args.no_others else other_workloads(A)
+    if others:
+        print("other workloads: %s" % json.dumps(others), file=sys.stderr)
+
     mix = None
     if args.mix_requests > 0:
         from paper_1012_0385_amd import workloads as W
@@ -274,6 +316,7 @@ def main():
         "batched": {"value": batched_value, "ms_per_step": t_batch / args.steps * 1e3},
         "roofline": roofline,
         "served_mix": mix,
+        "other_workloads": others,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -363,7 +363,7 @@ __host__ __device__ constexpr uint32_t sweep_max_block(int C, int model = kPlain
 // Lane lt owns window slots [lt*C, lt*C+C); slot i holds the 64 sites
 // starting at sig + 64*(base + off + i) (mod L).
 // ---------------------------------------------------------------------------
-template <int C, int MODEL, int V, bool Q0>
+template <int C, int MODEL, int V, bool Q0, bool MEAS>
 __device__ __forceinline__ void sweep_body(const SimDesc& P) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int NPL = (MODEL == kTwoLane) ? 2 : 1;
@@ -455,7 +455,7 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
                 lmask[pl * mwords + idx] = msrc[(size_t)pl * nw + w];
             }
     }
-    if (P.n_rec) build_byte_tables(tab1, tab2);
+    if (MEAS && P.n_rec) build_byte_tables(tab1, tab2);
     __syncthreads();
 
     uint32_t sig = 0, off = 0, buf = 0;
@@ -579,10 +579,12 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
     uint64_t shq = ~0ull;
     uint32_t ri = 0;
     for (uint64_t g = P.g0;; ++g) {
-        while (ri < P.n_rec && P.rec_g[ri] == g) {
-            shift_to(0);  // uniform call: rings of one workgroup may differ in sig
-            measure(ri);
-            ++ri;
+        if constexpr (MEAS) {
+            while (ri < P.n_rec && P.rec_g[ri] == g) {
+                shift_to(0);  // uniform call: rings of one workgroup may differ in sig
+                measure(ri);
+                ++ri;
+            }
         }
         if (g >= P.g1) break;
         const uint64_t quad = g >> 2;
@@ -695,17 +697,17 @@ __device__ __forceinline__ uint32_t find_desc(const SimDesc* __restrict__ d, uin
 }
 
 // One simulation per launch: the descriptor travels in the kernel arguments.
-template <int C, int MODEL, int V, bool Q0>
+template <int C, int MODEL, int V, bool Q0, bool MEAS>
 __global__ __launch_bounds__(sweep_max_block(C, MODEL)) void k_sweep(const SimDesc P) {
-    sweep_body<C, MODEL, V, Q0>(P);
+    sweep_body<C, MODEL, V, Q0, MEAS>(P);
 }
 
 // Packed launch: workgroups of several simulations (requests) in one grid,
 // each finding its descriptor in device memory.
-template <int C, int MODEL, int V, bool Q0>
+template <int C, int MODEL, int V, bool Q0, bool MEAS>
 __global__ __launch_bounds__(sweep_max_block(C, MODEL)) void k_sweep_packed(
     const SimDesc* __restrict__ descs, uint32_t n_desc) {
-    sweep_body<C, MODEL, V, Q0>(descs[find_desc(descs, n_desc, blockIdx.x)]);
+    sweep_body<C, MODEL, V, Q0, MEAS>(descs[find_desc(descs, n_desc, blockIdx.x)]);
 }
 
 // Dispatch of one model's kernels over (C, variant, q0).  Compiled variants:
@@ -713,17 +715,28 @@ __global__ __launch_bounds__(sweep_max_block(C, MODEL)) void k_sweep_packed(
 // 1 fields per word, each with and without backward hops; two lanes with 4 or
 // 1 fields per word.
 // Packed launches are compiled for the small-ring shapes (C <= 4).
+// Measurement code is compiled in only where a launch measures (it costs
+// registers, hence waves per SIMD).  A packed launch measures if any of its
+// simulations does (`one` then carries n_rec > 0).
 template <int MODEL, int C, int V, bool Q>
 inline void launch_one(const SimDesc& one, const SimDesc* descs, uint32_t n_desc, uint32_t grid,
                        uint32_t block, size_t lds, hipStream_t st) {
+    const bool meas = one.n_rec > 0;
     if constexpr (C <= 4) {
         if (descs) {
-            hipLaunchKernelGGL((k_sweep_packed<C, MODEL, V, Q>), dim3(grid), dim3(block), lds, st,
-                               descs, n_desc);
+            if (meas)
+                hipLaunchKernelGGL((k_sweep_packed<C, MODEL, V, Q, true>), dim3(grid), dim3(block),
+                                   lds, st, descs, n_desc);
+            else
+                hipLaunchKernelGGL((k_sweep_packed<C, MODEL, V, Q, false>), dim3(grid),
+                                   dim3(block), lds, st, descs, n_desc);
             return;
         }
     }
-    hipLaunchKernelGGL((k_sweep<C, MODEL, V, Q>), dim3(grid), dim3(block), lds, st, one);
+    if (meas)
+        hipLaunchKernelGGL((k_sweep<C, MODEL, V, Q, true>), dim3(grid), dim3(block), lds, st, one);
+    else
+        hipLaunchKernelGGL((k_sweep<C, MODEL, V, Q, false>), dim3(grid), dim3(block), lds, st, one);
 }
 
 template <int MODEL, int C, int V>

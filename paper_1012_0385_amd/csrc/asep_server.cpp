@@ -280,7 +280,11 @@ bool queue_packed(asep_server* S, const std::vector<Job*>& group, const PackInfo
     const uint32_t nd = (uint32_t)group.size();
     hipError_t e = hipMemcpyAsync(S->pack_dev[slot], hd, sizeof(SimDesc) * nd,
                                   hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = launch_sweep(pi.kern, hd[0], S->pack_dev[slot], nd, wg, pi.block, lds, st);
+    // the launch measures if any of its simulations does
+    SimDesc head = hd[0];
+    head.n_rec = 0;
+    for (uint32_t i = 0; i < nd; ++i) head.n_rec = std::max(head.n_rec, hd[i].n_rec);
+    if (e == hipSuccess) e = launch_sweep(pi.kern, head, S->pack_dev[slot], nd, wg, pi.block, lds, st);
     for (size_t i = 0; i < group.size(); ++i) {
         Job& j = *group[i];
         int rc = (e == hipSuccess) ? ASEP_OK : device_error(e, "packed launch");

@@ -121,6 +121,7 @@ if __name__ == "__main__":
 
     ap = argparse.ArgumentParser(description="tune launch shapes of the benchmark workloads")
     ap.add_argument("--t-max", type=int, default=2000)
+    ap.add_argument("--only", type=int, default=-1, help="tune only job i")
     ap.add_argument("--out", default=DEFAULT_TABLE)
     args = ap.parse_args()
     from .sim import sample_times
@@ -132,9 +133,18 @@ if __name__ == "__main__":
     jobs = [
         # the L = 2^17 KPZ + EW pair (run together)
         ([dict(L=1 << 17, p=1.0, q=0.0, seed=1, stream=0), dict(L=1 << 17, p=0.5, q=0.5, seed=1, stream=1)], 64),
+        # columnar disorder: 1024 realisations x 4 noise seeds of 2^16 sites
+        ([dict(L=1 << 16, p=1.0, q=0.0, slow_frac=0.1, slow_factor=0.5, samples_per_disorder=4,
+               seed=1, stream=2)], 4096),
+        # two lanes of 2^16 sites, 1024 samples
+        ([dict(L=1 << 16, model=1, init=1, density=0.3, p=1.0, q=1.0, lane_rate=0.1,
+               turn_frac=0.05, seed=1, stream=3)], 1024),
     ]
-    for kws, samples in jobs:
-        best = tune(kws, samples, times, verbose=True)
+    for i, (kws, samples) in enumerate(jobs):
+        if args.only >= 0 and i != args.only:
+            continue
+        jt = times if samples <= 256 else [t for t in times if t <= 300] + ([300] if times[-1] > 300 else [])
+        best = tune(kws, samples, jt, verbose=True)
         print("best", best, flush=True)
         for kw in kws:
             store(kw, samples, best, dev, args.out)
