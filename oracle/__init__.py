@@ -25,6 +25,8 @@ RING = 0
 TWO_LANE = 1
 INIT_FLAT = 0
 INIT_BERNOULLI = 1
+SCHED_SHIFTED = 0
+SCHED_SUBLATTICE = 1
 
 
 def build(force: bool = False) -> str:
@@ -56,6 +58,7 @@ class _Params(ctypes.Structure):
         ("cell_log2", ctypes.c_uint32),
         ("subsweeps", ctypes.c_uint32),
         ("rbits", ctypes.c_int32),
+        ("schedule", ctypes.c_uint32),
     ]
 
 
@@ -138,12 +141,14 @@ class Params:
     cell_log2: int = 6
     subsweeps: int = 4
     rbits: int = -1
+    schedule: int = SCHED_SHIFTED
 
     def c(self) -> _Params:
         return _Params(self.model, self.init, self.L, self.density, self.p, self.q,
                        self.slow_frac, self.slow_factor, self.samples_per_disorder,
                        self.lane_rate, self.turn_frac, self.seed & 0xFFFFFFFF,
-                       self.stream & 0xFFFFFFFF, self.cell_log2, self.subsweeps, self.rbits)
+                       self.stream & 0xFFFFFFFF, self.cell_log2, self.subsweeps, self.rbits,
+                       self.schedule)
 
     @property
     def planes(self) -> int:

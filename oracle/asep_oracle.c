@@ -104,8 +104,55 @@ uint64_t orc_threshold(double x, int bits) {
 
 static int is_pow2_log(uint32_t v) { return v >= 1 && v <= 30; }
 
+/* The paper's two-sub-lattice update (Sec. 2.1, Fig. parasep) has no cells:
+ * every pair of a sub-lattice is tried once per MCS with its own uniform
+ * B-bit number, B at most 24. */
+static int lower_sublattice(const orc_params *P, orc_sched *S) {
+    if (P->model != ORC_RING) return -1;
+    if (P->L < 4 || P->L % 2 != 0) return -1;
+    if (!(P->p >= 0 && P->p <= 1 && P->q >= 0 && P->q <= 1)) return -1;
+    const int BMAX = 24;
+    uint64_t t[4];
+    int nt = 0;
+    S->TB[0] = orc_threshold(P->p, BMAX);
+    S->TB[1] = orc_threshold(P->q, BMAX);
+    S->TB[2] = orc_threshold(P->slow_factor * P->p, BMAX);
+    S->TB[3] = orc_threshold(P->slow_factor * P->q, BMAX);
+    t[nt++] = S->TB[0];
+    t[nt++] = S->TB[1];
+    if (P->slow_frac > 0) {
+        t[nt++] = S->TB[2];
+        t[nt++] = S->TB[3];
+    }
+    int b;
+    if (P->rbits < 0) {
+        for (b = 0; b <= BMAX; ++b) {
+            int ok = 1;
+            for (int i = 0; i < nt; ++i)
+                if (t[i] % ((uint64_t)1 << (BMAX - b)) != 0) ok = 0;
+            if (ok) break;
+        }
+    } else {
+        b = P->rbits;
+        if (b > BMAX) return -1;
+        for (int i = 0; i < nt; ++i)
+            if (t[i] % ((uint64_t)1 << (BMAX - b)) != 0) return -1;
+    }
+    S->B = BMAX;
+    S->b = (uint32_t)b;
+    for (int i = 0; i < 4; ++i) S->T[i] = S->TB[i] >> (BMAX - b);
+    S->S = 2;
+    S->ell = 2;
+    S->T_init = orc_threshold(P->density, 32);
+    S->T_slow = orc_threshold(P->slow_frac, 32);
+    S->T_turn = 0;
+    return 0;
+}
+
 int orc_lower(const orc_params *P, orc_sched *S) {
     memset(S, 0, sizeof(*S));
+    if (P->schedule == ORC_SCHED_SUBLATTICE) return lower_sublattice(P, S);
+    if (P->schedule != ORC_SCHED_SHIFTED) return -1;
     if (!is_pow2_log(P->cell_log2)) return -1;
     uint32_t ell = 1u << P->cell_log2;
     int two = (P->model == ORC_TWO_LANE);
@@ -325,9 +372,68 @@ static void subsweep_two_lane(const orc_params *P, const orc_sched *S, uint32_t 
     }
 }
 
+/* ------------------------------------------------------------------------- */
+/* The paper's two-sub-lattice update (Sec. 2.1, Fig. parasep).  One MCS:    */
+/* phase 0 tries every pair (x, x+1) with x even, phase 1 every pair with x   */
+/* odd.  Pairs of one phase share no site, so their order is free; in phase  */
+/* 1 the pair (L-1, 0) that closes the ring is tried after the others, as in */
+/* the paper.  A tried pair "10" hops right if U < T_p[x], a pair "01" hops   */
+/* left if U < T_q[x+1] (rates of the departure site).                        */
+/*                                                                            */
+/* U is b bits.  Pair i of phase f (left site x = 2 i + f) belongs to group   */
+/* w = i / 32 at position m = i mod 32; bit (b-1-n) of U, n = 0..b-1 from the */
+/* top, is bit ((m mod 16) * 2 + m / 16) of random word n of group w, and     */
+/* random word n is word (n mod 4) of the Philox block at counter            */
+/* (w, lo32(g), 8 << 28 | (n / 4) << 16 | hi16(g), sample) with g = 2 t + f. */
+/* ------------------------------------------------------------------------- */
+#define TAG_SUBLATTICE 8u
+
+static void phase_sublattice(const orc_params *P, const orc_sched *S, uint32_t sample, uint64_t g,
+                             uint8_t *s, const uint8_t *slow_p, const uint8_t *slow_q, int64_t *J) {
+    const uint64_t L = P->L;
+    const uint64_t f = g % 2;
+    const uint64_t npairs = L / 2;
+    uint32_t words[24];
+    for (uint64_t i = 0; i < npairs; ++i) {
+        const uint64_t w = i / 32;
+        const uint32_t m = (uint32_t)(i % 32);
+        if (m == 0) {
+            for (uint32_t n = 0; n < S->b; n += 4) {
+                uint32_t out[4];
+                uint32_t c2 = (TAG_SUBLATTICE << 28) | ((n / 4) << 16) |
+                              (uint32_t)((g >> 32) & 0xFFFFu);
+                draw(P, (uint32_t)w, (uint32_t)(g & 0xFFFFFFFFu), c2, sample, out);
+                for (uint32_t k = 0; k < 4 && n + k < S->b; ++k) words[n + k] = out[k];
+            }
+        }
+        const uint32_t bit = (m % 16) * 2 + m / 16;
+        uint64_t u = 0;
+        for (uint32_t n = 0; n < S->b; ++n) u = (u << 1) | ((words[n] >> bit) & 1u);
+        const uint64_t x = 2 * i + f;
+        const uint64_t y = (x + 1) % L;
+        const uint64_t tp = (slow_p && slow_p[x]) ? S->T[2] : S->T[0];
+        const uint64_t tq = (slow_q && slow_q[y]) ? S->T[3] : S->T[1];
+        if (s[x] == 1 && s[y] == 0 && u < tp) {
+            s[x] = 0;
+            s[y] = 1;
+            *J += 1;
+        } else if (s[x] == 0 && s[y] == 1 && u < tq) {
+            s[x] = 1;
+            s[y] = 0;
+            *J -= 1;
+        }
+    }
+}
+
 void orc_sweep(const orc_params *P, const orc_sched *S, uint32_t sample, uint8_t *s,
                const uint8_t *mask_a, const uint8_t *mask_b, uint64_t t0, uint64_t n_mcs,
                int64_t *J) {
+    if (P->schedule == ORC_SCHED_SUBLATTICE) {
+        for (uint64_t t = t0; t < t0 + n_mcs; ++t)
+            for (uint64_t phase = 0; phase < 2; ++phase)
+                phase_sublattice(P, S, sample, 2 * t + phase, s, mask_a, mask_b, J);
+        return;
+    }
     for (uint64_t t = t0; t < t0 + n_mcs; ++t) {
         for (uint32_t sub = 0; sub < S->S; ++sub) {
             uint64_t g = t * S->S + sub;

@@ -12,6 +12,8 @@
 #define ORC_TWO_LANE 1
 #define ORC_INIT_FLAT 0
 #define ORC_INIT_BERNOULLI 1
+#define ORC_SCHED_SHIFTED 0
+#define ORC_SCHED_SUBLATTICE 1
 
 typedef struct {
     uint32_t model;     /* ORC_RING or ORC_TWO_LANE */
@@ -30,6 +32,7 @@ typedef struct {
     uint32_t cell_log2; /* ell = 2^cell_log2 */
     uint32_t subsweeps; /* S */
     int32_t rbits;      /* -1: fewest exact bits; else explicit */
+    uint32_t schedule;  /* ORC_SCHED_SHIFTED or ORC_SCHED_SUBLATTICE */
 } orc_params;
 
 typedef struct {

@@ -11,6 +11,9 @@ shares arithmetic with the simulators it checks.
   drawn uniformly from [0, ell), every cell of ell sites receives `a` attempts,
   each on a uniformly chosen offset j in [0, ell) with j = ell-1 a no-op; the
   cells act on disjoint sites, so their order does not matter;
+* the paper's two-sub-lattice update (Sec. 2.1, Fig. parasep): every pair
+  (x, x+1) with x even tried once, then every pair with x odd (the ring's
+  closing pair (L-1, 0) among them);
 * observables: W^2 per configuration (Eq. W with h_0 = 0, h_{x+1} = h_x + 1 -
   2 s_x) and the expected hop current.
 
@@ -133,6 +136,21 @@ class Ring:
                     total += float(u @ cur) / ell
                     u = self.cell_attempt(u, base, ell)
         return total
+
+    # --- the paper's two-sub-lattice update ----------------------------------
+    def sca_phase(self, v, f: int):
+        """Every pair (x, x+1) with x = f mod 2 tried once (disjoint pairs)."""
+        for x in range(f, self.L, 2):
+            v = self.bond(v, x)
+        return v
+
+    def sca_mcs(self, v):
+        return self.sca_phase(self.sca_phase(v, 0), 1)
+
+    def sca_phase_current(self, v, f: int) -> float:
+        """Expected hop count of one phase started from distribution v; the
+        pairs of a phase share no site, so each sees the phase's input law."""
+        return float(sum(v @ self.bond_current(x) for x in range(f, self.L, 2)))
 
 
 class TwoLane:
