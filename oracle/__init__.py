@@ -202,10 +202,10 @@ def init_masks(P: Params, realization: int):
     sq = np.zeros(P.L, np.uint8)
     tu = np.zeros(P.L, np.uint8)
     lib().orc_init_masks(ctypes.byref(pc), ctypes.byref(s), realization, _u8(sp), _u8(sq), _u8(tu))
-    if P.model == TWO_LANE:
+    if P.model == TWO_LANE and P.schedule != SCHED_SUBLATTICE:
         return None, None, tu
     if P.slow_frac > 0:
-        return sp, (sq if P.q > 0 else None), None
+        return sp, (sq if (P.q > 0 or P.model == TWO_LANE) else None), None
     return None, None, None
 
 

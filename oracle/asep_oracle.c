@@ -107,8 +107,15 @@ static int is_pow2_log(uint32_t v) { return v >= 1 && v <= 30; }
 /* The paper's two-sub-lattice update (Sec. 2.1, Fig. parasep) has no cells:
  * every pair of a sub-lattice is tried once per MCS with its own uniform
  * B-bit number, B at most 24. */
+/* Two lanes (Sec. 3, the SCA sequence): in-lane hops of A (right, p) and B   */
+/* (left, q) on the sub-lattices, lane changes at every site with u_x (A to   */
+/* B) and v_x (B to A) equal to the lane rate, times the slow factor where    */
+/* the site's u (v) mark is set; T = {p, q, lane rate, slow factor x lane     */
+/* rate}.  Four steps per MCS (see sweep_two_lane_sublattice).               */
 static int lower_sublattice(const orc_params *P, orc_sched *S) {
-    if (P->model != ORC_RING) return -1;
+    const int two = P->model == ORC_TWO_LANE;
+    if (P->model != ORC_RING && !two) return -1;
+    if (two && P->turn_frac != 0) return -1;
     if (P->L < 4 || P->L % 2 != 0) return -1;
     if (!(P->p >= 0 && P->p <= 1 && P->q >= 0 && P->q <= 1)) return -1;
     const int BMAX = 24;
@@ -116,12 +123,18 @@ static int lower_sublattice(const orc_params *P, orc_sched *S) {
     int nt = 0;
     S->TB[0] = orc_threshold(P->p, BMAX);
     S->TB[1] = orc_threshold(P->q, BMAX);
-    S->TB[2] = orc_threshold(P->slow_factor * P->p, BMAX);
-    S->TB[3] = orc_threshold(P->slow_factor * P->q, BMAX);
+    if (two) {
+        S->TB[2] = orc_threshold(P->lane_rate, BMAX);
+        S->TB[3] = orc_threshold(P->slow_factor * P->lane_rate, BMAX);
+    } else {
+        S->TB[2] = orc_threshold(P->slow_factor * P->p, BMAX);
+        S->TB[3] = orc_threshold(P->slow_factor * P->q, BMAX);
+    }
     t[nt++] = S->TB[0];
     t[nt++] = S->TB[1];
+    if (two) t[nt++] = S->TB[2];
     if (P->slow_frac > 0) {
-        t[nt++] = S->TB[2];
+        if (!two) t[nt++] = S->TB[2];
         t[nt++] = S->TB[3];
     }
     int b;
@@ -141,7 +154,7 @@ static int lower_sublattice(const orc_params *P, orc_sched *S) {
     S->B = BMAX;
     S->b = (uint32_t)b;
     for (int i = 0; i < 4; ++i) S->T[i] = S->TB[i] >> (BMAX - b);
-    S->S = 2;
+    S->S = two ? 4 : 2;
     S->ell = 2;
     S->T_init = orc_threshold(P->density, 32);
     S->T_slow = orc_threshold(P->slow_frac, 32);
@@ -425,9 +438,96 @@ static void phase_sublattice(const orc_params *P, const orc_sched *S, uint32_t s
     }
 }
 
+/* ------------------------------------------------------------------------- */
+/* Two lanes under the paper's SCA sequence (Sec. 3): one MCS is             */
+/*   g = 4t:   even pairs of A (hop right, p) and of B (hop left, q);        */
+/*   g = 4t+1: A -> B at every site (A occupied, B empty) with u_x;          */
+/*   g = 4t+2: odd pairs of A and B, the closing pair (L-1, 0) among them    */
+/*             (the paper's steps 3 and 4, disjoint pairs);                  */
+/*   g = 4t+3: B -> A at every site (B occupied, A empty) with v_x.          */
+/* J counts A hops minus B hops.  Random numbers: Philox blocks at counter   */
+/* (w, lo32(g), 8 << 28 | blk << 16 | hi16(g), sample), word k of the step  */
+/* being word k mod 4 of block k / 4.  In-lane: pair i (left site 2i + f)    */
+/* is in group w = i / 32 at m = i mod 32, and bit b-1-n of lane A's U is    */
+/* bit (m mod 16) * 2 + m / 16 of word 2n, of lane B's U the same bit of     */
+/* word 2n+1.  Lane changes: site x is in group w = x / 64 at s = x mod 64,  */
+/* and bit b-1-n of its U is bit s mod 32 of word 2n + s / 32.               */
+/* ------------------------------------------------------------------------- */
+static void draw_words(const orc_params *P, uint32_t sample, uint64_t g, uint64_t w, uint32_t n,
+                       uint32_t *words) {
+    for (uint32_t k = 0; k < n; k += 4) {
+        uint32_t out[4];
+        uint32_t c2 = (TAG_SUBLATTICE << 28) | ((k / 4) << 16) | (uint32_t)((g >> 32) & 0xFFFFu);
+        draw(P, (uint32_t)w, (uint32_t)(g & 0xFFFFFFFFu), c2, sample, out);
+        for (uint32_t i = 0; i < 4 && k + i < n; ++i) words[k + i] = out[i];
+    }
+}
+
+static void inlane_two(const orc_params *P, const orc_sched *S, uint32_t sample, uint64_t g,
+                       uint64_t f, uint8_t *a, uint8_t *b, int64_t *J) {
+    const uint64_t L = P->L;
+    uint32_t words[48];
+    for (uint64_t i = 0; i < L / 2; ++i) {
+        const uint32_t m = (uint32_t)(i % 32);
+        if (m == 0) draw_words(P, sample, g, i / 32, 2 * S->b, words);
+        const uint32_t bit = (m % 16) * 2 + m / 16;
+        uint64_t ua = 0, ub = 0;
+        for (uint32_t n = 0; n < S->b; ++n) {
+            ua = (ua << 1) | ((words[2 * n] >> bit) & 1u);
+            ub = (ub << 1) | ((words[2 * n + 1] >> bit) & 1u);
+        }
+        const uint64_t x = 2 * i + f;
+        const uint64_t y = (x + 1) % L;
+        if (a[x] == 1 && a[y] == 0 && ua < S->T[0]) {
+            a[x] = 0;
+            a[y] = 1;
+            *J += 1;
+        }
+        if (b[y] == 1 && b[x] == 0 && ub < S->T[1]) {
+            b[y] = 0;
+            b[x] = 1;
+            *J -= 1;
+        }
+    }
+}
+
+static void lane_change_two(const orc_params *P, const orc_sched *S, uint32_t sample, uint64_t g,
+                            uint8_t *from, uint8_t *to, const uint8_t *mark) {
+    const uint64_t L = P->L;
+    uint32_t words[48];
+    for (uint64_t x = 0; x < L; ++x) {
+        const uint32_t sx = (uint32_t)(x % 64);
+        if (sx == 0) draw_words(P, sample, g, x / 64, 2 * S->b, words);
+        uint64_t u = 0;
+        for (uint32_t n = 0; n < S->b; ++n)
+            u = (u << 1) | ((words[2 * n + sx / 32] >> (sx % 32)) & 1u);
+        const uint64_t thr = (mark && mark[x]) ? S->T[3] : S->T[2];
+        if (from[x] == 1 && to[x] == 0 && u < thr) {
+            from[x] = 0;
+            to[x] = 1;
+        }
+    }
+}
+
+static void sweep_two_lane_sublattice(const orc_params *P, const orc_sched *S, uint32_t sample,
+                                      uint8_t *s, const uint8_t *umark, const uint8_t *vmark,
+                                      uint64_t t0, uint64_t n_mcs, int64_t *J) {
+    uint8_t *a = s, *b = s + P->L;
+    for (uint64_t t = t0; t < t0 + n_mcs; ++t) {
+        inlane_two(P, S, sample, 4 * t, 0, a, b, J);
+        lane_change_two(P, S, sample, 4 * t + 1, a, b, umark);
+        inlane_two(P, S, sample, 4 * t + 2, 1, a, b, J);
+        lane_change_two(P, S, sample, 4 * t + 3, b, a, vmark);
+    }
+}
+
 void orc_sweep(const orc_params *P, const orc_sched *S, uint32_t sample, uint8_t *s,
                const uint8_t *mask_a, const uint8_t *mask_b, uint64_t t0, uint64_t n_mcs,
                int64_t *J) {
+    if (P->schedule == ORC_SCHED_SUBLATTICE && P->model == ORC_TWO_LANE) {
+        sweep_two_lane_sublattice(P, S, sample, s, mask_a, mask_b, t0, n_mcs, J);
+        return;
+    }
     if (P->schedule == ORC_SCHED_SUBLATTICE) {
         for (uint64_t t = t0; t < t0 + n_mcs; ++t)
             for (uint64_t phase = 0; phase < 2; ++phase)
@@ -474,6 +574,22 @@ double orc_w2(uint64_t L, int64_t S1, uint64_t S2_lo, int64_t S2_hi) {
     return (double)num / ((double)L * (double)L);
 }
 
+/* Quenched planes of one realisation: the turning plane of the shifted     */
+/* two-lane model; the slow-p (u) and slow-q (v) planes of a disordered ring */
+/* (q plane only if q > 0) or of the two-lane SCA.                           */
+static void alloc_masks(const orc_params *P, const orc_sched *S, uint32_t realization,
+                        uint8_t **ma, uint8_t **mb) {
+    const int sca_two = P->model == ORC_TWO_LANE && P->schedule == ORC_SCHED_SUBLATTICE;
+    if (P->model == ORC_TWO_LANE && !sca_two) {
+        *ma = (uint8_t *)calloc(P->L, 1);
+        orc_init_masks(P, S, realization, NULL, NULL, *ma);
+    } else if (P->slow_frac > 0) {
+        *ma = (uint8_t *)calloc(P->L, 1);
+        if (P->q > 0 || sca_two) *mb = (uint8_t *)calloc(P->L, 1);
+        orc_init_masks(P, S, realization, *ma, *mb, NULL);
+    }
+}
+
 /* Full run of one sample: init, then for each requested time t (ascending,
  * t = 0 meaning the initial state) advance to t and record (S1, S2, J, N). */
 int orc_run(const orc_params *P, uint32_t sample, const uint64_t *times, uint32_t n_times,
@@ -487,14 +603,7 @@ int orc_run(const orc_params *P, uint32_t sample, const uint64_t *times, uint32_
     uint32_t realization = sample / spd;
     if (!s) return -2;
     orc_init_state(P, &S, sample, s);
-    if (P->model == ORC_TWO_LANE) {
-        ma = (uint8_t *)calloc(P->L, 1);
-        orc_init_masks(P, &S, realization, NULL, NULL, ma);
-    } else if (P->slow_frac > 0) {
-        ma = (uint8_t *)calloc(P->L, 1);
-        if (P->q > 0) mb = (uint8_t *)calloc(P->L, 1);
-        orc_init_masks(P, &S, realization, ma, mb, NULL);
-    }
+    alloc_masks(P, &S, realization, &ma, &mb);
     int64_t J = 0;
     uint64_t t = 0;
     for (uint32_t i = 0; i < n_times; ++i) {
@@ -529,14 +638,7 @@ int orc_advance(const orc_params *P, uint32_t sample, uint8_t *s, uint64_t t0, u
     uint8_t *ma = NULL, *mb = NULL;
     uint32_t spd = P->samples_per_disorder ? P->samples_per_disorder : 1;
     uint32_t realization = sample / spd;
-    if (P->model == ORC_TWO_LANE) {
-        ma = (uint8_t *)calloc(P->L, 1);
-        orc_init_masks(P, &S, realization, NULL, NULL, ma);
-    } else if (P->slow_frac > 0) {
-        ma = (uint8_t *)calloc(P->L, 1);
-        if (P->q > 0) mb = (uint8_t *)calloc(P->L, 1);
-        orc_init_masks(P, &S, realization, ma, mb, NULL);
-    }
+    alloc_masks(P, &S, realization, &ma, &mb);
     orc_sweep(P, &S, sample, s, ma, mb, t0, n_mcs, J);
     free(ma);
     free(mb);

@@ -248,6 +248,33 @@ class TwoLane:
         return total
 
 
+    # --- the paper's two-lane SCA sequence -----------------------------------
+    def sca_inlane(self, v, f: int):
+        """Pairs (x, x+1), x = f mod 2: A hops right w.p. pa, B hops left w.p.
+        pb, each lane's pair tried once (disjoint bits, so the order is free)."""
+        for x in range(f, self.L, 2):
+            v = self._move(v, self._ahop[x], self.pa)
+            v = self._move(v, self._bhop[x], self.pb)
+        return v
+
+    def sca_inlane_current(self, v, f: int) -> float:
+        return float(sum(v @ self.event_current(x, e, False)
+                         for x in range(f, self.L, 2) for e in (0, 1)))
+
+    def lane_change(self, v, to_b: bool, prob):
+        """Every site once: A -> B (to_b) or B -> A with probability prob[x]."""
+        moves = self._ab if to_b else self._ba
+        for x in range(self.L):
+            v = self._move(v, moves[x], prob[x])
+        return v
+
+    def sca_mcs(self, v, u, w):
+        v = self.sca_inlane(v, 0)
+        v = self.lane_change(v, True, u)
+        v = self.sca_inlane(v, 1)
+        return self.lane_change(v, False, w)
+
+
 def stationary(step, v0: np.ndarray, tol: float = 1e-14, max_iter: int = 200000) -> np.ndarray:
     """Fixed point of a stochastic map by iteration from v0."""
     v = v0.copy()

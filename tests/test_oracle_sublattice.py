@@ -46,7 +46,7 @@ def test_sublattice_rejects_other_shapes(orc):
     with pytest.raises(ValueError):
         orc.lower(_sca(orc, L=255))
     with pytest.raises(ValueError):
-        orc.lower(_sca(orc, L=256, model=orc.TWO_LANE))
+        orc.lower(_sca(orc, L=256, model=orc.TWO_LANE, turn_frac=0.05))
 
 
 @pytest.mark.parametrize("L", [8, 256, 4096])
@@ -164,3 +164,80 @@ def test_sublattice_conservation_and_chunks(orc):
     J = orc.advance(P, 7, st, 4, 5, J)
     J = orc.advance(P, 7, st, 9, 16, J)
     assert J == full.J[-1] and np.array_equal(st, full.state)
+
+
+# --------------------------------------------------------------------------- two lanes
+def _sca2(orc, **kw):
+    base = dict(model=orc.TWO_LANE, init=orc.INIT_BERNOULLI, density=0.5, p=0.5, q=0.5,
+                lane_rate=0.8, slow_frac=0.5, slow_factor=0.25)
+    base.update(kw)
+    return orc.Params(schedule=orc.SCHED_SUBLATTICE, **base)
+
+
+def test_two_lane_sublattice_lowering(orc):
+    # Sec. 3: in-lane 0.5, crossing 0.8 reduced to 0.2 at marked sites
+    s = orc.lower(_sca2(orc, L=256))
+    assert s["S"] == 4 and s["b"] == 24
+    assert s["T"] == [1 << 23, 1 << 23, 0xCCCCCC, int(0.2 * 2 ** 24)]
+    with pytest.raises(ValueError):
+        orc.lower(_sca2(orc, L=256, turn_frac=0.1))
+
+
+def test_two_lane_sublattice_invariants(orc):
+    P = _sca2(orc, L=1024)
+    r = orc.run(P, 3, [0, 5, 20])
+    assert len(set(r.N.tolist())) == 1
+    # no lane changes: each lane keeps its particle number, and p = q = 1 on
+    # lanes started flat is the one-lane degeneracy in both directions
+    P0 = _sca2(orc, L=1024, lane_rate=0.0, p=1.0, q=1.0, init=orc.INIT_FLAT)
+    st0 = orc.init_state(P0, 3)
+    r0 = orc.run(P0, 3, [0, 1, 7])
+    assert r0.state[:1024].sum() == st0[:1024].sum() and r0.state[1024:].sum() == st0[1024:].sum()
+    # from 1010... in both lanes: A hops at every pair of both phases (+L per
+    # MCS); B, hopping left, misses the even phase of the first MCS and then
+    # follows A's pattern mirrored (-L/2, then -L per MCS)
+    assert list(r0.J) == [0, 512, 512]
+    # the marks: two independent planes of density 1/2 keyed by realisation
+    sp, sq, tu = orc.init_masks(_sca2(orc, L=1 << 14), 0)
+    assert tu is None and abs(sp.mean() - 0.5) < 0.02 and abs(sq.mean() - 0.5) < 0.02
+    assert abs((sp & sq).mean() - 0.25) < 0.02
+
+
+def test_two_lane_sublattice_law_exact(orc):
+    L, t, n = 4, 2, 6000
+    P = _sca2(orc, L=L, p=0.75, q=0.5, lane_rate=0.8, slow_factor=0.25, seed=9)
+    s = orc.lower(P)
+    um, vm, _ = orc.init_masks(P, 0)
+    assert um.any() or vm.any()
+    den = 2 ** s["b"]
+    u = np.where(um == 1, s["T"][3] / den, s["T"][2] / den)
+    w = np.where(vm == 1, s["T"][3] / den, s["T"][2] / den)
+    tl = me.TwoLane(L, s["T"][0] / den, s["T"][1] / den, 0.0, np.zeros(L))
+    rho = s["T_init"] / 2 ** 32
+    bits = me.bits_table(L, 2).astype(np.float64)
+    v = np.prod(np.where(bits == 1, rho, 1 - rho), axis=1)
+    for _ in range(t):
+        v = tl.sca_mcs(v, u, w)
+    P.samples_per_disorder = n
+    assert _chi2_pvalue(_histogram(orc, P, t, n), v, n) > 1e-4
+
+
+def test_two_lane_sublattice_current_exact(orc):
+    L, t, n = 4, 3, 6000
+    P = _sca2(orc, L=L, p=0.75, q=0.25, lane_rate=0.5, slow_frac=0.0, seed=4)
+    s = orc.lower(P)
+    den = 2 ** s["b"]
+    tl = me.TwoLane(L, s["T"][0] / den, s["T"][1] / den, 0.0, np.zeros(L))
+    u = np.full(L, s["T"][2] / den)
+    rho = s["T_init"] / 2 ** 32
+    bits = me.bits_table(L, 2).astype(np.float64)
+    v = np.prod(np.where(bits == 1, rho, 1 - rho), axis=1)
+    mean = 0.0
+    for _ in range(t):
+        mean += tl.sca_inlane_current(v, 0)
+        v = tl.lane_change(tl.sca_inlane(v, 0), True, u)
+        mean += tl.sca_inlane_current(v, 1)
+        v = tl.lane_change(tl.sca_inlane(v, 1), False, u)
+    js = np.array([orc.run(P, k, [t]).J[-1] for k in range(n)], dtype=np.float64)
+    z = (js.mean() - mean) / (js.std(ddof=1) / np.sqrt(n))
+    assert abs(z) < 4.5, (js.mean(), mean)
