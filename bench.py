@@ -159,6 +159,12 @@ def other_workloads(A, t_cut=1000):
         ("two_lane_L2p16", dict(L=1 << 16, model=1, init=1, density=0.3, p=1.0, q=1.0,
                                 lane_rate=0.1, turn_frac=0.05, seed=1, stream=3), 1024, None,
          "1024 two-lane rings of 2^16 per lane, first %d of 10^5 MCS" % t_cut),
+        ("sca_L2p17", dict(L=1 << 17, p=0.8, q=0.0, seed=1, stream=4, schedule=1), 64, None,
+         "64 rings of 2^17, the paper's two-sub-lattice update at p = 0.8, first %d MCS" % t_cut),
+        ("qssep_sca_L2p15", dict(L=1 << 15, p=0.5, q=0.5, slow_frac=0.5, slow_factor=0.2, seed=1,
+                                 stream=5, schedule=1), 120, None,
+         "Q-SSEP (Q = 0.5, r = 0.2, p = q = 0.5), 120 realisations of 2^15, two-sub-lattice "
+         "update, first %d MCS" % t_cut),
     ]
     for name, kw, samples, times, desc in cases:
         if times is None:

@@ -22,7 +22,10 @@
  * starting at sigma; every cell receives ell/S (two lanes: 4 ell/S)
  * random-sequential attempts on a uniformly chosen offset j, the offset
  * j = ell-1 (the bond leaving the cell) being a no-op.  Cells are disjoint,
- * so all of them are updated at once.  Random numbers are Philox4x32-10
+ * so all of them are updated at once.  The paper's own two-sub-lattice
+ * update (Sec. 2.1, Fig. parasep) is the second schedule (asep_params.schedule):
+ * S = 2 sub-sweeps, the first trying every pair (x, x+1) with x even once,
+ * the second every pair with x odd.  Random numbers are Philox4x32-10
  * blocks keyed by (seed, stream) with counters built from (cell, g, sample),
  * so a result depends only on the parameters, never on how the work is
  * batched, chunked or laid out on the device.
@@ -46,7 +49,7 @@
 extern "C" {
 #endif
 
-#define ASEP_ABI_VERSION 1u
+#define ASEP_ABI_VERSION 2u
 
 enum {
     ASEP_OK = 0,
@@ -63,6 +66,7 @@ enum {
 
 enum { ASEP_MODEL_RING = 0, ASEP_MODEL_TWO_LANE = 1 };
 enum { ASEP_INIT_FLAT = 0, ASEP_INIT_BERNOULLI = 1 };
+enum { ASEP_SCHED_SHIFTED = 0, ASEP_SCHED_SUBLATTICE = 1 };
 
 /* Run parameters.  Zero-initialise, then set abi_version = ASEP_ABI_VERSION. */
 typedef struct asep_params {
@@ -79,8 +83,11 @@ typedef struct asep_params {
     double density;    /* Bernoulli start, in [0,1] */
     double p;          /* ring: right-hop probability; two lanes: lane A (rightward) */
     double q;          /* ring: left-hop probability;  two lanes: lane B (leftward) */
-    double slow_frac;  /* ring: fraction of slow sites (Eq. bimodal's Q), [0,1] */
-    double slow_factor;/* ring: rate factor r of slow sites, [0,1] */
+    double slow_frac;  /* ring: fraction of slow sites (Eq. bimodal's Q), [0,1];
+                          two lanes under ASEP_SCHED_SUBLATTICE: fraction of
+                          marked sites in each of the u and v planes */
+    double slow_factor;/* ring: rate factor r of slow sites; two-lane SCA:
+                          lane-change factor at marked sites; [0,1] */
     double lane_rate;  /* two lanes: lane-change probability at a turning point */
     double turn_frac;  /* two lanes: fraction of turning points, [0,1] */
     uint32_t seed;     /* Philox key word 0 */
@@ -96,6 +103,20 @@ typedef struct asep_params {
     uint32_t window_sweeps; /* sub-sweeps per launch of a windowed ring; 0 = 63 */
     uint32_t rings_per_wg;  /* launch shape only: whole rings packed per
                                workgroup; 0 = automatic */
+    uint32_t schedule; /* ASEP_SCHED_SHIFTED (the shifted cells above) or
+                          ASEP_SCHED_SUBLATTICE, the paper's SCA:
+                          rings (Sec. 2.1, Fig. parasep): every pair (x, x+1)
+                          with x even tried once, then every pair with x odd,
+                          the closing pair (L-1, 0) among them; cell_log2 and
+                          subsweeps must be 0 or 1 and 2;
+                          two lanes (Sec. 3's sequence): even pairs of A and B,
+                          A -> B at every site with u_x, odd pairs, B -> A with
+                          v_x; u_x = v_x = lane_rate, times slow_factor where
+                          the site's u (v) mark is set (marks: independent
+                          Bernoulli(slow_frac) planes); turn_frac must be 0,
+                          cell_log2 and subsweeps 0 or 1 and 4.
+                          Each tried pair or site compares a 24-bit uniform
+                          with its threshold (rbits as above, at most 24) */
 } asep_params;
 
 /* Roughness and current of one sample at one time (Sec. 2.1, Eq. W).

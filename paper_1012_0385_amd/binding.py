@@ -13,7 +13,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libasep.so")
 
-ASEP_ABI_VERSION = 1
+ASEP_ABI_VERSION = 2
 ASEP_OK = 0
 ASEP_E_INVAL = -1
 ASEP_E_UNSUPPORTED = -2
@@ -28,6 +28,8 @@ ASEP_MODEL_RING = 0
 ASEP_MODEL_TWO_LANE = 1
 ASEP_INIT_FLAT = 0
 ASEP_INIT_BERNOULLI = 1
+ASEP_SCHED_SHIFTED = 0
+ASEP_SCHED_SUBLATTICE = 1
 
 
 class asep_params(ctypes.Structure):
@@ -54,6 +56,7 @@ class asep_params(ctypes.Structure):
         ("windows", ctypes.c_uint32),
         ("window_sweeps", ctypes.c_uint32),
         ("rings_per_wg", ctypes.c_uint32),
+        ("schedule", ctypes.c_uint32),
     ]
 
 

@@ -8,6 +8,7 @@
 //   shift:   (0, lo32(g/4), 2<<28 | hi16(g/4), sample), word g mod 4
 //   init:    (site/4, lane, 3<<28, sample), word site mod 4
 //   masks:   (site/4, 0, tag<<28, realisation), word site mod 4
+//   two-sub-lattice update: (slot w, lo32(g), 8<<28 | blk<<16 | hi16(g), sample)
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -285,6 +286,177 @@ __device__ __forceinline__ int32_t cell_two_lane_fast(uint64_t& xa, uint64_t& xb
     return dj;
 }
 
+// The paper's two-sub-lattice update (Sec. 2.1, Fig. parasep) on one slot:
+// the slot holds the 64 sites starting at an even site (phase 0) or an odd
+// one (phase 1), so the 32 pairs of the phase sit at bits (2m, 2m+1) and the
+// ring's closing pair is the top pair of the last slot.  Every pair is tried
+// once: "10" hops right if U < T_p of its left site, "01" hops left if
+// U < T_q of its right site, with U a b-bit number per pair.  The pairs are
+// handled bit-parallel: pair m takes bit c(m) = 2 (m mod 16) + m / 16 of the
+// random words, so the pair masks fold into 32 bits with one shift and one
+// or (the left-site bits of the high half move next to those of the low
+// half).  Random word n holds bit b-1-n of every U (most significant first);
+// word n of the comparison is word n mod 4 of Philox block n / 4.  The
+// comparison runs from the top bit and stops, block by block, as soon as
+// every live pair of the slot is decided; a pair still equal to its
+// threshold once the threshold's remaining bits are all zero is decided too
+// (U >= T).  The result is that of the full b-bit comparison, with most of
+// the blocks never drawn.
+__device__ __forceinline__ uint32_t fold_pairs(uint64_t m) {
+    return (uint32_t)m | ((uint32_t)(m >> 32) << 1);
+}
+
+__device__ __forceinline__ uint64_t unfold_pairs(uint32_t a) {
+    return (uint64_t)(a & 0x55555555u) | ((uint64_t)((a >> 1) & 0x55555555u) << 32);
+}
+
+template <bool Q0, bool DIS>
+__device__ __forceinline__ int32_t sca_slot(uint64_t& x, uint64_t m0, uint64_t m1,
+                                            const CellCtx& c) {
+    constexpr uint64_t kEven = 0x5555555555555555ull;
+    const uint64_t l = x & kEven;
+    const uint64_t r = (x >> 1) & kEven;
+    const uint32_t fw = fold_pairs(l & ~r);
+    const uint32_t bw = Q0 ? 0u : fold_pairs(r & ~l);
+    // pair classes: forward at a fast/slow left site, backward at a fast/slow right site
+    const uint32_t sp = DIS ? fold_pairs(m0 & kEven) : 0u;
+    const uint32_t sq = (DIS && !Q0) ? fold_pairs((m1 >> 1) & kEven) : 0u;
+    const uint32_t cls[4] = {fw & ~sp, Q0 ? 0u : (bw & ~sq), fw & sp, Q0 ? 0u : (bw & sq)};
+    const uint32_t thr[4] = {c.T0, c.T1, c.T2, c.T3};
+    const uint32_t full = 1u << c.b;
+    uint32_t acc = 0, und = 0;
+    uint32_t depth[4];  // leading bits that decide a comparison with thr[i]
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        depth[i] = 0;
+        if (thr[i] >= full) {
+            acc |= cls[i];
+        } else if (thr[i] != 0) {
+            und |= cls[i];
+            depth[i] = c.b - (uint32_t)__builtin_ctz(thr[i]);
+        }
+    }
+    uint32_t lt = 0;
+    for (uint32_t blk = 0; und != 0u && blk < c.nblk; ++blk) {
+        const Blk rb = philox(c.k, c.glo, c.c2b | (blk << 16), c.sample, c.k0, c.k1);
+#pragma unroll
+        for (int wd = 0; wd < 4; ++wd) {
+            const uint32_t n = blk * 4u + (uint32_t)wd;
+            if (n < c.b) {
+                const uint32_t kb = c.b - 1u - n;
+                uint32_t t = 0;
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (!(Q0 && (i & 1)) && (DIS || i < 2))
+                        t |= cls[i] & (0u - ((thr[i] >> kb) & 1u));
+                const uint32_t u = rb.v[wd];
+                lt |= und & t & ~u;
+                und &= ~(t ^ u);
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (!(Q0 && (i & 1)) && (DIS || i < 2))
+                        if (n + 1u == depth[i]) und &= ~cls[i];
+            }
+        }
+    }
+    acc |= lt;
+    const uint64_t a64 = unfold_pairs(acc);
+    x ^= a64 | (a64 << 1);
+    if (Q0) return __popc(acc);
+    return __popc(acc & fw) - __popc(acc & bw);
+}
+
+// One bit plane of a lazy bit-sliced comparison U < T from the top bit:
+// `t` marks the pairs (sites) whose threshold has a 1 at this bit, `u` holds
+// this bit of their U.  Pairs where u < t become accepted, pairs where they
+// differ leave the undecided set.
+template <typename W>
+__device__ __forceinline__ void cmp_plane(W& lt, W& und, W t, W u) {
+    lt |= und & t & ~u;
+    und &= ~(t ^ u);
+}
+
+// Accept-all / undecided split of one threshold class, and the number of
+// leading bits that decide it (the bits below its lowest 1 are all zero).
+template <typename W>
+__device__ __forceinline__ uint32_t sca_class(W cls, uint32_t thr, uint32_t b, W& acc, W& und) {
+    if (thr >= (1u << b)) {
+        acc |= cls;
+        return 0;
+    }
+    if (thr == 0) return 0;
+    und |= cls;
+    return b - (uint32_t)__builtin_ctz(thr);
+}
+
+// Two lanes, the paper's SCA sequence (Sec. 3), in-lane step on the pairs
+// at bits (2m, 2m+1) of the slot: A's "10" hops right if U_A < T0, B's "01"
+// hops left if U_B < T1.  Bit b-1-n of U_A is bit c(m) of the step's word
+// 2n, of U_B of word 2n+1 (Philox block n / 2 gives A's planes in words 0
+// and 2, B's in words 1 and 3).  Returns A hops minus B hops.
+__device__ __forceinline__ int32_t sca_two_inlane(uint64_t& xa, uint64_t& xb, const CellCtx& c) {
+    constexpr uint64_t kEven = 0x5555555555555555ull;
+    const uint64_t la = xa & kEven, ra = (xa >> 1) & kEven;
+    const uint64_t lb = xb & kEven, rb = (xb >> 1) & kEven;
+    const uint32_t fa = fold_pairs(la & ~ra);
+    const uint32_t fb = fold_pairs(rb & ~lb);
+    uint32_t acc_a = 0, acc_b = 0, und_a = 0, und_b = 0, lt_a = 0, lt_b = 0;
+    const uint32_t da = sca_class(fa, c.T0, c.b, acc_a, und_a);
+    const uint32_t db = sca_class(fb, c.T1, c.b, acc_b, und_b);
+    for (uint32_t blk = 0; (und_a | und_b) != 0u && blk < c.nblk; ++blk) {
+        const Blk r = philox(c.k, c.glo, c.c2b | (blk << 16), c.sample, c.k0, c.k1);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const uint32_t n = 2u * blk + (uint32_t)j;
+            if (n < c.b) {
+                const uint32_t kb = c.b - 1u - n;
+                cmp_plane(lt_a, und_a, fa & (0u - ((c.T0 >> kb) & 1u)), r.v[2 * j]);
+                cmp_plane(lt_b, und_b, fb & (0u - ((c.T1 >> kb) & 1u)), r.v[2 * j + 1]);
+                if (n + 1u == da) und_a = 0;
+                if (n + 1u == db) und_b = 0;
+            }
+        }
+    }
+    acc_a |= lt_a;
+    acc_b |= lt_b;
+    const uint64_t ma = unfold_pairs(acc_a), mb = unfold_pairs(acc_b);
+    xa ^= ma | (ma << 1);
+    xb ^= mb | (mb << 1);
+    return __popc(acc_a) - __popc(acc_b);
+}
+
+// Two lanes, lane-change step: every site with a particle in `from` and a
+// hole in `to` moves across if U < T2 (T3 where `mark` is set).  Bit b-1-n
+// of a site's U is bit (s mod 32) of the step's word 2n + s / 32, s the
+// site's bit in the slot (Philox block n / 2 holds planes 2 blk, 2 blk + 1).
+__device__ __forceinline__ void sca_two_change(uint64_t& from, uint64_t& to, uint64_t mark,
+                                               const CellCtx& c) {
+    const uint64_t live = from & ~to;
+    const uint64_t c0 = live & ~mark, c1 = live & mark;
+    uint64_t acc = 0, und = 0, lt = 0;
+    const uint32_t d0 = sca_class(c0, c.T2, c.b, acc, und);
+    const uint32_t d1 = sca_class(c1, c.T3, c.b, acc, und);
+    for (uint32_t blk = 0; und != 0u && blk < c.nblk; ++blk) {
+        const Blk r = philox(c.k, c.glo, c.c2b | (blk << 16), c.sample, c.k0, c.k1);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const uint32_t n = 2u * blk + (uint32_t)j;
+            if (n < c.b) {
+                const uint32_t kb = c.b - 1u - n;
+                const uint64_t u = (uint64_t)r.v[2 * j] | ((uint64_t)r.v[2 * j + 1] << 32);
+                const uint64_t t = (c0 & (0ull - ((c.T2 >> kb) & 1u))) |
+                                   (c1 & (0ull - ((c.T3 >> kb) & 1u)));
+                cmp_plane(lt, und, t, u);
+                if (n + 1u == d0) und &= ~c0;
+                if (n + 1u == d1) und &= ~c1;
+            }
+        }
+    }
+    const uint64_t flip = acc | lt;
+    from ^= flip;
+    to ^= flip;
+}
+
 // Variants of the attempt loop.  The fast ones need ell = 64 and the default
 // four sub-sweeps per MCS (16 attempts per cell and sub-sweep on one lane,
 // 64 on two lanes).
@@ -295,6 +467,7 @@ enum Variant : int {
     kF4B2 = 3,  // 4 fields per word, 2 threshold bits
     kF1 = 4,    // 1 field per word, threshold bits at run time
     kF4B0 = 5,  // two lanes: 4 fields per word, no threshold bits
+    kSca = 6,   // the paper's sub-lattice updates (both models, every slot shape)
 };
 
 template <int V>
@@ -367,7 +540,7 @@ template <int C, int MODEL, int V, bool Q0, bool MEAS>
 __device__ __forceinline__ void sweep_body(const SimDesc& P) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int NPL = (MODEL == kTwoLane) ? 2 : 1;
-    constexpr bool FAST = V != kGeneric;
+    constexpr bool FAST = V != kGeneric && V != kSca;
     constexpr int AV = VarInfo<V>::A;
     constexpr int BV = VarInfo<V>::BB;
 
@@ -587,23 +760,35 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
             }
         }
         if (g >= P.g1) break;
-        const uint64_t quad = g >> 2;
-        if (quad != shq) {
-            const Blk r = philox(0u, (uint32_t)quad,
-                                 (kTagShift << 28) | (uint32_t)((quad >> 32) & 0xFFFFu), sample,
-                                 cc.k0, cc.k1);
-            shblk[0] = r.v[0];
-            shblk[1] = r.v[1];
-            shblk[2] = r.v[2];
-            shblk[3] = r.v[3];
-            shq = quad;
+        // SCA step: single lane even / odd pairs; two lanes even pairs,
+        // A -> B, odd pairs, B -> A.  g is the same for the whole workgroup,
+        // so skipping the exchange when the frame stays is a uniform branch.
+        const uint32_t step = (MODEL == kTwoLane) ? (uint32_t)(g & 3u) : (uint32_t)(g & 1u);
+        if constexpr (V == kSca) {
+            // the odd pairs are the only step in the frame starting at odd
+            // sites; lane changes draw their bits in the even frame
+            const uint32_t frame = (MODEL == kTwoLane) ? (step == 2u ? 1u : 0u) : step;
+            if (frame != sig) shift_to(frame);
+            cc.c2b = (kTagSublattice << 28) | (uint32_t)((g >> 32) & 0xFFFFu);
+        } else {
+            const uint64_t quad = g >> 2;
+            if (quad != shq) {
+                const Blk r = philox(0u, (uint32_t)quad,
+                                     (kTagShift << 28) | (uint32_t)((quad >> 32) & 0xFFFFu),
+                                     sample, cc.k0, cc.k1);
+                shblk[0] = r.v[0];
+                shblk[1] = r.v[1];
+                shblk[2] = r.v[2];
+                shblk[3] = r.v[3];
+                shq = quad;
+            }
+            const uint32_t gq = (uint32_t)(g & 3u);
+            const uint32_t sw =
+                gq == 0 ? shblk[0] : gq == 1 ? shblk[1] : gq == 2 ? shblk[2] : shblk[3];
+            shift_to(sw & cmask);
+            cc.c2b = (kTagAttempt << 28) | (uint32_t)((g >> 32) & 0xFFFFu);
         }
-        const uint32_t gq = (uint32_t)(g & 3u);
-        const uint32_t sw = gq == 0 ? shblk[0] : gq == 1 ? shblk[1] : gq == 2 ? shblk[2] : shblk[3];
-        shift_to(sw & cmask);
-
         cc.glo = (uint32_t)g;
-        cc.c2b = (kTagAttempt << 28) | (uint32_t)((g >> 32) & 0xFFFFu);
         // word of the window position of slot 0 of this lane
         uint32_t wb = base + off + base_slot;
         while (wb >= nw) wb -= nw;
@@ -617,7 +802,7 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
                 uint64_t xa = sa[i];
                 uint64_t xb = sb[i];
                 uint64_t m0 = 0, m1 = 0;
-                if (MODEL != kPlain) {
+                if (MODEL != kPlain && P.mplanes > 0) {
                     uint32_t ia, ib;
                     if (seg) {
                         ia = min(pos, mwords - 2);
@@ -627,11 +812,23 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
                         ib = (w + 1 == nw) ? 0 : w + 1;
                     }
                     m0 = funnel(lmask[ia], lmask[ib], sig);
-                    if (MODEL == kDisorder && P.mplanes > 1)
+                    if ((MODEL == kDisorder || V == kSca) && P.mplanes > 1)
                         m1 = funnel(lmask[mwords + ia], lmask[mwords + ib], sig);
                 }
                 int32_t d = 0;
-                if constexpr (FAST) {
+                if constexpr (V == kSca) {
+                    cc.k = w;
+                    if constexpr (MODEL == kTwoLane) {
+                        if ((step & 1u) == 0)
+                            d = sca_two_inlane(xa, xb, cc);
+                        else if (step == 1)
+                            sca_two_change(xa, xb, m0, cc);  // A -> B, u marks
+                        else
+                            sca_two_change(xb, xa, m1, cc);  // B -> A, v marks
+                    } else {
+                        d = sca_slot<Q0, MODEL == kDisorder>(xa, m0, m1, cc);
+                    }
+                } else if constexpr (FAST) {
                     cc.k = w;
                     if (MODEL == kTwoLane)
                         d = cell_two_lane_fast<AV, BV, 64>(xa, xb, m0, cc);
@@ -742,10 +939,14 @@ inline void launch_one(const SimDesc& one, const SimDesc* descs, uint32_t n_desc
 template <int MODEL, int C, int V>
 inline void launch_q(const SweepKernel& k, const SimDesc& one, const SimDesc* descs,
                      uint32_t n_desc, uint32_t grid, uint32_t block, size_t lds, hipStream_t st) {
-    if (MODEL != kTwoLane && k.q0)
-        launch_one<MODEL, C, V, true>(one, descs, n_desc, grid, block, lds, st);
-    else
+    if constexpr (MODEL == kTwoLane) {
         launch_one<MODEL, C, V, false>(one, descs, n_desc, grid, block, lds, st);
+    } else {
+        if (k.q0)
+            launch_one<MODEL, C, V, true>(one, descs, n_desc, grid, block, lds, st);
+        else
+            launch_one<MODEL, C, V, false>(one, descs, n_desc, grid, block, lds, st);
+    }
 }
 
 template <int MODEL, int C>
@@ -753,6 +954,14 @@ inline hipError_t launch_c(const SweepKernel& k, const SimDesc& one, const SimDe
                            uint32_t n_desc, uint32_t grid, uint32_t block, size_t lds,
                            hipStream_t st) {
     if (descs && C > 4) return hipErrorInvalidValue;
+    if (k.variant == kSca) {
+        // two lanes hold twice the state: 16 slots per lane would spill
+        if constexpr (MODEL != kTwoLane || C <= 8) {
+            launch_q<MODEL, C, kSca>(k, one, descs, n_desc, grid, block, lds, st);
+            return hipSuccess;
+        }
+        return hipErrorInvalidValue;
+    }
     if (k.variant == kGeneric) {
         launch_one<MODEL, C, kGeneric, false>(one, descs, n_desc, grid, block, lds, st);
         return hipSuccess;
@@ -799,6 +1008,7 @@ inline hipError_t launch_model(const SweepKernel& k, const SimDesc& one, const S
 inline bool variant_compiled(uint32_t C, uint32_t model, uint32_t variant) {
     if (C != 1 && C != 2 && C != 4 && C != 8 && C != 16) return false;
     if (variant == kGeneric) return true;
+    if (variant == kSca) return model != kTwoLane || C <= 8;
     if (C > 8) return false;
     if (model == kTwoLane) return variant == kF4B0 || variant == kF1;
     return variant == kF5B0 || variant == kF4B1 || variant == kF4B2 || variant == kF1;

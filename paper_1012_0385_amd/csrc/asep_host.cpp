@@ -66,6 +66,21 @@ static int resolve(const asep_params* in, Resolved* r) {
     if (!in) return ASEP_E_INVAL;
     if (in->abi_version != ASEP_ABI_VERSION) return ASEP_E_INVAL;
     asep_params P = *in;
+    if (P.schedule != ASEP_SCHED_SHIFTED && P.schedule != ASEP_SCHED_SUBLATTICE)
+        return ASEP_E_INVAL;
+    const bool sca = P.schedule == ASEP_SCHED_SUBLATTICE;
+    if (sca) {
+        // pairs of two sites; single lane: even pairs, odd pairs (S = 2);
+        // two lanes: even pairs, A -> B, odd pairs, B -> A (S = 4)
+        const int32_t S_sca = P.model == ASEP_MODEL_TWO_LANE ? 4 : 2;
+        if ((P.cell_log2 != 0 && P.cell_log2 != 1) || (P.subsweeps != 0 && P.subsweeps != S_sca))
+            return ASEP_E_INVAL;
+        // the two-lane sequence changes lanes at every site (bimodal rates
+        // through the slow marks), so there is no turning-point plane
+        if (P.model == ASEP_MODEL_TWO_LANE && P.turn_frac != 0) return ASEP_E_INVAL;
+        P.cell_log2 = 1;
+        P.subsweeps = S_sca;
+    }
     if (P.cell_log2 == 0) P.cell_log2 = 6;
     if (P.subsweeps == 0) P.subsweeps = 4;
     if (P.samples_per_disorder == 0) P.samples_per_disorder = 1;
@@ -82,7 +97,7 @@ static int resolve(const asep_params* in, Resolved* r) {
     const bool two = P.model == ASEP_MODEL_TWO_LANE;
     const uint32_t per_mcs = (uint32_t)(two ? 4 * ell : ell);
     if (P.subsweeps < 1 || per_mcs % (uint32_t)P.subsweeps != 0) return ASEP_E_INVAL;
-    if (two && P.slow_frac > 0) return ASEP_E_UNSUPPORTED;
+    if (two && !sca && P.slow_frac > 0) return ASEP_E_UNSUPPORTED;
     if ((uint64_t)P.sample_offset + P.samples > 0x100000000ull) return ASEP_E_INVAL;
 
     Sched sc{};
@@ -90,7 +105,9 @@ static int resolve(const asep_params* in, Resolved* r) {
     sc.S = (uint32_t)P.subsweeps;
     sc.a = per_mcs / sc.S;
     const int ebits = two ? 2 : 0;
-    const int B = 32 - (int)sc.lam - ebits;
+    // draw width: the shifted schedule packs [j | e | r] into 32 bits; the
+    // two-sub-lattice update compares a 24-bit uniform per pair
+    const int B = sca ? 24 : 32 - (int)sc.lam - ebits;
     uint64_t TB[4] = {0, 0, 0, 0};
     std::vector<uint64_t> used;
     if (!two) {
@@ -108,6 +125,10 @@ static int resolve(const asep_params* in, Resolved* r) {
         TB[1] = lower_prob(P.q, B);
         TB[2] = lower_prob(P.lane_rate, B);
         used = {TB[0], TB[1], TB[2]};
+        if (sca) {
+            TB[3] = lower_prob(P.slow_factor * P.lane_rate, B);  // marked sites
+            if (P.slow_frac > 0) used.push_back(TB[3]);
+        }
     }
     auto exact_at = [&](int b) {
         const uint64_t unit = uint64_t(1) << (B - b);
@@ -126,9 +147,17 @@ static int resolve(const asep_params* in, Resolved* r) {
     P.rbits = b;
     sc.b = (uint32_t)b;
     for (int i = 0; i < 4; ++i) sc.T[i] = (uint32_t)(TB[i] >> (B - b));
-    sc.w = sc.lam + (uint32_t)ebits + sc.b;
-    sc.A = 32 / sc.w;
-    sc.nblk = (sc.a + 4 * sc.A - 1) / (4 * sc.A);
+    if (sca) {
+        sc.w = 0;
+        sc.A = 0;
+        // one random bit plane per compared bit: 32 pairs or sites per word;
+        // two lanes draw two words per plane (A and B pairs, or 64 sites)
+        sc.nblk = two ? (sc.b + 1) / 2 : (sc.b + 3) / 4;
+    } else {
+        sc.w = sc.lam + (uint32_t)ebits + sc.b;
+        sc.A = 32 / sc.w;
+        sc.nblk = (sc.a + 4 * sc.A - 1) / (4 * sc.A);
+    }
     sc.T_init = lower_prob(P.density, 32);
     sc.T_slow = lower_prob(P.slow_frac, 32);
     sc.T_turn = lower_prob(P.turn_frac, 32);
@@ -138,7 +167,13 @@ static int resolve(const asep_params* in, Resolved* r) {
     r->planes = two ? 2 : 1;
     r->nw = (uint32_t)(P.L / 64);
     r->spd = P.samples_per_disorder;
-    if (two) {
+    if (two && sca) {
+        r->model = kTwoLane;  // u (A -> B) and v (B -> A) marks, if any
+        r->mplanes = P.slow_frac > 0 ? 2 : 0;
+        r->mtags[0] = kTagDisP;
+        r->mtags[1] = kTagDisQ;
+        r->T_mask = sc.T_slow;
+    } else if (two) {
         r->model = kTwoLane;
         r->mplanes = 1;
         r->mtags[0] = r->mtags[1] = kTagTurn;
@@ -208,7 +243,9 @@ static SweepKernel pick_kernel(const Resolved& r, uint32_t C) {
     k.variant = 0;
     const Sched& sc = r.sc;
     const bool two = r.model == kTwoLane;
-    if (sc.lam == 6 && sc.a == (two ? 64u : 16u)) {
+    if (r.P.schedule == ASEP_SCHED_SUBLATTICE) {
+        k.variant = 6;  // the paper's sub-lattice updates
+    } else if (sc.lam == 6 && sc.a == (two ? 64u : 16u)) {
         uint32_t v = 0;
         if (!two) {
             if (sc.A == 5 && sc.b == 0) v = 1;
@@ -232,6 +269,7 @@ static bool plan_whole(const Resolved& r, Plan* p) {
     const uint32_t nw = r.nw, R = r.P.samples;
     static const uint32_t Cs[] = {1, 2, 4, 8, 16};
     for (uint32_t C : Cs) {
+        if (!sweep_variant_compiled(C, r.model, pick_kernel(r, C).variant)) continue;
         const uint32_t maxb = sweep_block_limit(C, r.model);
         const uint32_t Tr = (nw + C - 1) / C;
         if (Tr > maxb) continue;
@@ -272,6 +310,7 @@ static bool plan_windows(const Resolved& r, uint32_t segs, uint32_t K, Plan* p) 
     if (nslot + halo + 2 > 4 * (uint64_t)nw) return false;
     static const uint32_t Cs[] = {1, 2, 4, 8};
     for (uint32_t C : Cs) {
+        if (!sweep_variant_compiled(C, r.model, pick_kernel(r, C).variant)) continue;
         const uint32_t maxb = sweep_block_limit(C, r.model);
         const uint32_t Tr = (nslot + C - 1) / C;
         if (Tr > maxb) continue;

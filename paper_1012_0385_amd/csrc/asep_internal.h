@@ -15,6 +15,7 @@ enum : uint32_t {
     kTagDisP = 4,
     kTagDisQ = 5,
     kTagTurn = 6,
+    kTagSublattice = 8,
 };
 
 // One measurement of one ring (exact integers; W^2 is formed on the host).

@@ -20,7 +20,8 @@ def make_params(L: int, samples: int = 1, *, model: int = B.ASEP_MODEL_RING,
                 samples_per_disorder: int = 1, lane_rate: float = 0.0, turn_frac: float = 0.0,
                 seed: int = 1, stream: int = 0, cell_log2: int = 0, subsweeps: int = 0,
                 rbits: int = -1, sample_offset: int = 0, windows: int = 0,
-                window_sweeps: int = 0, rings_per_wg: int = 0) -> B.asep_params:
+                window_sweeps: int = 0, rings_per_wg: int = 0,
+                schedule: int = B.ASEP_SCHED_SHIFTED) -> B.asep_params:
     P = B.asep_params()
     P.abi_version = B.ASEP_ABI_VERSION
     P.model = model
@@ -44,6 +45,7 @@ def make_params(L: int, samples: int = 1, *, model: int = B.ASEP_MODEL_RING,
     P.windows = windows
     P.window_sweeps = window_sweeps
     P.rings_per_wg = rings_per_wg
+    P.schedule = schedule
     return P
 
 

@@ -9,7 +9,8 @@ The update rule itself (cell size, sub-sweeps per MCS) is not tuned here: it
 defines the trajectory and stays the caller's choice.
 
 Tables are JSON: {"version": ..., "device": ..., "entries": {key: shape}},
-key = "model:L:samples:cell_log2:subsweeps:rbits", shape = {"windows": w,
+key = "model:L:samples:cell_log2:subsweeps:rbits" (plus ":s1" for the
+two-sub-lattice schedule), shape = {"windows": w,
 "window_sweeps": k, "rings_per_wg": g, "rate": attempts/s}.
 """
 from __future__ import annotations
@@ -26,8 +27,11 @@ DEFAULT_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning
 
 
 def key_of(kw: dict, samples: int) -> str:
-    return "%d:%d:%d:%d:%d:%d" % (kw.get("model", 0), kw["L"], samples, kw.get("cell_log2", 0),
-                                  kw.get("subsweeps", 0), kw.get("rbits", -1))
+    key = "%d:%d:%d:%d:%d:%d" % (kw.get("model", 0), kw["L"], samples, kw.get("cell_log2", 0),
+                                 kw.get("subsweeps", 0), kw.get("rbits", -1))
+    if kw.get("schedule", 0):
+        key += ":s%d" % kw["schedule"]
+    return key
 
 
 def candidates(L: int, samples: int, n_cu: int = 256):
@@ -139,6 +143,11 @@ if __name__ == "__main__":
         # two lanes of 2^16 sites, 1024 samples
         ([dict(L=1 << 16, model=1, init=1, density=0.3, p=1.0, q=1.0, lane_rate=0.1,
                turn_frac=0.05, seed=1, stream=3)], 1024),
+        # the paper's two-sub-lattice update, 64 rings of 2^17 at p = 0.8
+        ([dict(L=1 << 17, p=0.8, q=0.0, seed=1, stream=4, schedule=1)], 64),
+        # Q-SSEP under the two-sub-lattice update: 120 realisations of 2^15
+        ([dict(L=1 << 15, p=0.5, q=0.5, slow_frac=0.5, slow_factor=0.2, seed=1, stream=5,
+               schedule=1)], 120),
     ]
     for i, (kws, samples) in enumerate(jobs):
         if args.only >= 0 and i != args.only:

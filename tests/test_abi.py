@@ -48,6 +48,21 @@ def test_host_only_entry_points(lib, orc):
     assert sb.value == 64 * (1 << 17) // 8
     bad = A.make_params(L=1000, samples=1)
     assert lib.asep_buffer_sizes(ctypes.byref(bad), ctypes.byref(sb), ctypes.byref(ab)) == B.ASEP_E_INVAL
+    # the sub-lattice schedules: ell = 2, S = 2 (rings) or 4 (two lanes)
+    SUB = B.ASEP_SCHED_SUBLATTICE
+    for kw, rc in [(dict(L=4096), 0), (dict(L=64), 0), (dict(L=4096, cell_log2=1, subsweeps=2), 0),
+                   (dict(L=4096, cell_log2=6), B.ASEP_E_INVAL),
+                   (dict(L=4096, subsweeps=4), B.ASEP_E_INVAL),
+                   (dict(L=4096, rbits=25), B.ASEP_E_INVAL),
+                   (dict(L=4096, p=0.8, rbits=21), B.ASEP_E_INVAL),
+                   (dict(L=4096, model=1, slow_frac=0.5, slow_factor=0.25, lane_rate=0.8), 0),
+                   (dict(L=4096, model=1, subsweeps=4), 0),
+                   (dict(L=4096, model=1, subsweeps=2), B.ASEP_E_INVAL),
+                   (dict(L=4096, model=1, turn_frac=0.05), B.ASEP_E_INVAL)]:
+        P = A.make_params(samples=2, schedule=SUB, **kw)
+        assert lib.asep_buffer_sizes(ctypes.byref(P), ctypes.byref(sb), ctypes.byref(ab)) == rc, kw
+    P = A.make_params(L=4096, samples=1, schedule=2)
+    assert lib.asep_buffer_sizes(ctypes.byref(P), ctypes.byref(sb), ctypes.byref(ab)) == B.ASEP_E_INVAL
     # ensemble W^2 of two flat rings is the intrinsic width 1/4
     arr = (B.asep_rough * 2)()
     for i in range(2):

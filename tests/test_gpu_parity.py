@@ -35,7 +35,7 @@ def oracle_params(orc, kw):
         lane_rate=kw.get("lane_rate", 0.0), turn_frac=kw.get("turn_frac", 0.0),
         seed=kw.get("seed", 1), stream=kw.get("stream", 0),
         cell_log2=kw.get("cell_log2", 6) or 6, subsweeps=kw.get("subsweeps", 4) or 4,
-        rbits=kw.get("rbits", -1))
+        rbits=kw.get("rbits", -1), schedule=kw.get("schedule", 0))
 
 
 def compare(orc, kw, times, samples, check_states=True, buffers="torch"):
