@@ -36,6 +36,41 @@ PEAK_SLOTS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock: 32-bit VALU sl
 PHILOX_SLOTS = 100  # 10 rounds x (2 quarter-rate 32x32->64 products + 2 xor3)
 UPDATE_SLOTS = 10   # field extraction, pair test, thresholds, flip, hop count
 
+# HBM traffic of one sweep launch at the tuned launch shape: rocprofv3 --pmc
+# FETCH_SIZE and WRITE_SIZE (KiB per dispatch, mean over the sweep dispatches
+# of `bench.py --t-max 2000 --steps 1 --warmup 0 --no-cpu --mix-requests 0
+# --no-others --form plain`), scaled by what the same counters read for a 4 GiB
+# device-to-device copy (`bench.py --calibrate-copy-mib 4096`).  They hold
+# only for the kernel sources they were taken on (SHA-256 prefix below) and
+# for that launch shape; otherwise the bench reports traffic as unknown.
+SWEEP_TRAFFIC = {
+    "src_sha256": "e4de18d06998a284",
+    "launch_shape": {"windows": 4, "window_sweeps": 255, "rings_per_wg": 0},
+    "fetch_kib": 830.75,   # KPZ 825.2, EW 836.3
+    "write_kib": 1032.0,
+    "fetch_scale": 2.0,    # 4 GiB copy: FETCH_SIZE 2097206 KiB
+    "write_scale": 1.0,    # 4 GiB copy: WRITE_SIZE 4194304 KiB
+}
+SWEEP_SOURCES = ("asep_device.h", "asep_internal.h", "asep_sweep_plain.hip")
+
+
+def sweep_source_hash() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for name in SWEEP_SOURCES:
+        with open(os.path.join(ROOT, "paper_1012_0385_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def sweep_traffic_bytes(shape):
+    """HBM bytes per sweep launch, or None where the counters do not apply."""
+    t = SWEEP_TRAFFIC
+    if t["src_sha256"] != sweep_source_hash() or t["launch_shape"] != shape:
+        return None
+    return (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024
+
 
 def alu_slots_per_attempt(sim):
     """Algorithmic 32-bit VALU slots per attempt for a simulation's schedule."""
@@ -165,6 +200,11 @@ def other_workloads(A, t_cut=1000):
                                  stream=5, schedule=1), 120, None,
          "Q-SSEP (Q = 0.5, r = 0.2, p = q = 0.5), 120 realisations of 2^15, two-sub-lattice "
          "update, first %d MCS" % t_cut),
+        ("two_lane_sca_L2p12", dict(L=1 << 12, model=1, init=1, density=0.5, p=0.5, q=0.5,
+                                    lane_rate=0.8, slow_frac=0.5, slow_factor=0.25, seed=1,
+                                    stream=6, schedule=1), 1024, None,
+         "the paper's two-lane SCA sequence (in-lane 0.5, crossing 0.8 / 0.2 bimodal), "
+         "1024 rings of 2^12 per lane, first %d MCS" % t_cut),
     ]
     for name, kw, samples, times, desc in cases:
         if times is None:
@@ -197,6 +237,9 @@ def main():
     ap.add_argument("--mix-requests", type=int, default=48, help="served-mix requests (0: skip)")
     ap.add_argument("--mix-load", type=float, default=0.8)
     ap.add_argument("--no-others", action="store_true", help="skip the other workload shapes")
+    ap.add_argument("--form", choices=("both", "plain"), default="both",
+                    help="plain: time only the one-after-the-other form (value = plain), "
+                         "so that a kernel trace holds no overlapped launches")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a device-to-device copy of this many MiB (counter scale)")
     args = ap.parse_args()
@@ -258,7 +301,7 @@ def main():
         return time.perf_counter() - t0
 
     for _ in range(args.warmup):
-        step_batched()
+        step_batched() if args.form == "both" else step_plain()
     # plain form, with kernel timing on: launches of one ensemble never
     # overlap, so each event pair times one kernel alone
     for s in sims:
@@ -268,7 +311,7 @@ def main():
     for s in sims:
         s.profile(False)
     # batched form
-    t_batch = timed(step_batched, args.steps)
+    t_batch = timed(step_batched, args.steps) if args.form == "both" else t_plain
     print("plain %.3f s, batched %.3f s over %d steps" % (t_plain, t_batch, args.steps),
           file=sys.stderr)
 
@@ -281,7 +324,8 @@ def main():
     avg_ms = kernel_ms / launches
     achieved = slots / launches / (avg_ms * 1e-3)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12,
-                "unit": "TOP/s", "frac": achieved / PEAK_SLOTS, "traffic": None,
+                "unit": "TOP/s", "frac": achieved / PEAK_SLOTS,
+                "traffic": sweep_traffic_bytes(shapes[0]),
                 "kernel": "k_sweep", "avg_launch_ms": avg_ms, "launches": launches}
 
     others = None if args.no_others else other_workloads(A)
@@ -319,7 +363,8 @@ def main():
                    "launch_shape": shapes[0] or "automatic",
                    "measurements": len(times), "parallelism": "1 GPU"},
         "plain": {"value": plain_value, "ms_per_step": t_plain / args.steps * 1e3},
-        "batched": {"value": batched_value, "ms_per_step": t_batch / args.steps * 1e3},
+        "batched": ({"value": batched_value, "ms_per_step": t_batch / args.steps * 1e3}
+                    if args.form == "both" else None),
         "roofline": roofline,
         "served_mix": mix,
         "other_workloads": others,

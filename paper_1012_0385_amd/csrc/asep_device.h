@@ -526,13 +526,66 @@ __host__ __device__ constexpr uint32_t sweep_max_block(int C, int model = kPlain
     return (C == 1 || (C == 2 && model != kTwoLane)) ? 1024u : 512u;
 }
 
+// Slot drift of a window over the launch's sub-sweeps [g0, g1): the number
+// of times the cell frame wraps (its start moves back below the previous
+// one), including the return to frame 0 at the end.  Each wrap moves the
+// slot labels one word to the right.  The shifted schedule's frames are the
+// Philox shift draws of the ring (lane l of the wave draws quad g0/4 + l, a
+// shuffle hands each quad the last frame of the one before); the sub-lattice
+// schedules' frames are fixed.  Every lane of the wave must call this (the
+// loop bounds are uniform); every lane gets the total.
+template <int MODEL, int V>
+__device__ uint32_t window_drift(const SimDesc& P, uint32_t sample, uint32_t cmask) {
+    const uint64_t g0 = P.g0, g1 = P.g1;
+    if (g1 <= g0) return 0;
+    if constexpr (V == kSca) {
+        // single lane: frames 0,1,0,1,... wrap at every even g; two lanes:
+        // frames 0,0,1,0 wrap at g = 3 mod 4; plus the return to frame 0
+        if constexpr (MODEL == kTwoLane)
+            return (uint32_t)(g1 / 4 - (g0 + 1) / 4) + (((g1 - 1) & 3u) == 2u ? 1u : 0u);
+        else
+            return (uint32_t)((g1 - 1) / 2 - g0 / 2) + (uint32_t)((g1 - 1) & 1u);
+    } else {
+        const uint32_t lane = threadIdx.x & 63u;
+        const uint64_t qlast = (g1 - 1) >> 2;
+        uint32_t carry = 0, total = 0;
+        for (uint64_t qb = g0 >> 2; qb <= qlast; qb += 64) {
+            const uint64_t q = qb + lane;
+            const Blk r = philox(0u, (uint32_t)q, (kTagShift << 28) | (uint32_t)((q >> 32) & 0xFFFFu),
+                                 sample, P.key0, P.key1);
+            uint32_t sg[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) sg[j] = r.v[j] & cmask;
+            uint32_t prev = (uint32_t)__shfl_up((int)sg[3], 1, 64);
+            if (lane == 0) prev = carry;
+            uint32_t c = 0;
+            if (q <= qlast) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const uint64_t g = 4 * q + (uint64_t)j;
+                    const uint32_t p = j == 0 ? prev : sg[j - 1];
+                    if (g > g0 && g < g1 && sg[j] < p) ++c;
+                    if (g + 1 == g1 && sg[j] != 0u) ++c;
+                }
+            }
+#pragma unroll
+            for (int m = 32; m >= 1; m >>= 1) c += (uint32_t)__shfl_xor((int)c, m, 64);
+            total += c;
+            carry = (uint32_t)__shfl((int)sg[3], 63, 64);
+        }
+        return total;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // The sweep kernel.  A workgroup serves either G whole rings (segs == 1:
 // the ring is periodic, measurements may be taken inside the launch) or one
-// window of one ring (segs > 1): output words [s0, s0+n) plus `halo` words
-// on each side, advanced by at most halo-1 sub-sweeps; garbage enters the
-// window from its right end one slot per sub-sweep and the window drifts
-// right by at most one slot per sub-sweep, so the output words are exact.
+// window of one ring (segs > 1): output words [s0, s0+n) plus the next
+// K+1 words, with the window's start placed d words before s0, d being the
+// exact slot drift of this launch (window_drift).  Garbage enters a window
+// only from its right end, at most one slot per frame change (K sub-sweeps
+// plus the return to frame 0), and the slot labels move right by exactly d,
+// so the output words are exact.
 // Lane lt owns window slots [lt*C, lt*C+C); slot i holds the 64 sites
 // starting at sig + 64*(base + off + i) (mod L).
 // ---------------------------------------------------------------------------
@@ -568,9 +621,12 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
     // window origin (whole ring: 0) and the output range in window positions
     const uint32_t s0 = sidx * P.seg_n;
     const uint32_t nout = seg ? min(P.seg_n, nw - s0) : nw;
-    const uint32_t halo = seg ? P.halo : 0;
-    const uint32_t base = seg ? (s0 + nw - halo) % nw : 0;
-    const uint32_t mwords = seg ? nslot + halo + 2 : nw;
+    // left margin: the exact drift of this launch (windows), 0 for whole rings
+    const uint32_t lm =
+        seg ? window_drift<MODEL, V>(P, P.sample0 + lb / P.segs, (1u << P.sc.lam) - 1u) : 0;
+    const uint32_t base = seg ? (s0 + nw - lm) % nw : 0;
+    // mask words staged: every position a slot can reach, plus one
+    const uint32_t mwords = seg ? nslot + P.halo + 2 : nw;
 
     size_t o_mask, o_red, o_scan, o_tab, o_g0;
     sweep_lds_layout(block, NPL, G, P.mplanes, mwords, &o_mask, &o_red, &o_scan, &o_tab, &o_g0);
@@ -847,7 +903,7 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
                 sa[i] = xa;
                 if (MODEL == kTwoLane) sb[i] = xb;
                 // a window counts the hops of the cells it owns
-                if (!seg || pos - halo < nout) dj += d;
+                if (!seg || pos - lm < nout) dj += d;
             }
         }
         J += dj;
@@ -857,7 +913,7 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
     for (int i = 0; i < C; ++i) {
         if (i < cnt) {
             const uint32_t pos = off + base_slot + (uint32_t)i;
-            if (!seg || pos - halo < nout) {
+            if (!seg || pos - lm < nout) {
                 uint32_t w = base + pos;
                 while (w >= nw) w -= nw;
                 uint64_t* dst = P.words_out + (size_t)ring * NPL * nw;

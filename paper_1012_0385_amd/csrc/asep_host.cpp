@@ -305,8 +305,10 @@ static bool plan_windows(const Resolved& r, uint32_t segs, uint32_t K, Plan* p) 
     if (segs < 2 || segs > nw) return false;
     const uint32_t seg_n = (nw + segs - 1) / segs;
     if ((uint64_t)(segs - 1) * seg_n >= nw) return false;  // every window owns words
+    // the window starts exactly its drift (at most K+1 words) before its
+    // output and reaches K+1 words past it (the garbage depth)
     const uint32_t halo = K + 1;
-    const uint32_t nslot = seg_n + 2 * halo;
+    const uint32_t nslot = seg_n + halo;
     if (nslot + halo + 2 > 4 * (uint64_t)nw) return false;
     static const uint32_t Cs[] = {1, 2, 4, 8};
     for (uint32_t C : Cs) {
