@@ -58,6 +58,14 @@ __device__ __forceinline__ uint64_t funnel(uint64_t lo, uint64_t hi, uint32_t sh
     return (lo >> sh) | ((hi << 1) << (63u - sh));
 }
 
+// Value of `v` in lane `src` of the wave (two 32-bit lane permutes); every
+// lane of the wave must execute it.
+__device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src) {
+    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, src, 64);
+    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), src, 64);
+    return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+
 __device__ __forceinline__ uint32_t bfe(uint32_t v, uint32_t off, uint32_t width) {
     return __builtin_amdgcn_ubfe(v, off, width);
 }
@@ -687,6 +695,9 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
     if (MEAS && P.n_rec) build_byte_tables(tab1, tab2);
     __syncthreads();
 
+    // whole rings of at most one wave each (lanes_per_ring a power of two
+    // up to 64, so no ring straddles two waves) exchange across lanes
+    const bool wsync = !seg && Tr <= 64u && (64u % Tr) == 0u;
     uint32_t sig = 0, off = 0, buf = 0;
     int64_t J = 0;
     const int64_t hops0 = (ring_ok && !seg) ? P.hops[ring] : 0;
@@ -695,15 +706,26 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
     auto shift_to = [&](uint32_t sig_new) {
         const uint32_t delta = (sig_new - sig) & 63u;
         const bool wrap = sig_new < sig;
-        uint64_t* xb = xch + (size_t)buf * block * NPL;
-        if (act) {
-            xb[tid * NPL] = sa[0];
-            if (MODEL == kTwoLane) xb[tid * NPL + 1] = sb[0];
+        uint64_t na_ = 0, nb_ = 0;
+        if (wsync) {
+            // the ring lies inside one wave: read the neighbour lane's first
+            // slot across lanes (every lane takes part), no barrier
+            const int src = (int)(nxt & 63u);
+            na_ = shfl_u64(sa[0], src);
+            if (MODEL == kTwoLane) nb_ = shfl_u64(sb[0], src);
+        } else {
+            uint64_t* xb = xch + (size_t)buf * block * NPL;
+            if (act) {
+                xb[tid * NPL] = sa[0];
+                if (MODEL == kTwoLane) xb[tid * NPL + 1] = sb[0];
+            }
+            __syncthreads();
+            if (act) {
+                na_ = xb[nxt * NPL];
+                if (MODEL == kTwoLane) nb_ = xb[nxt * NPL + 1];
+            }
         }
-        __syncthreads();
         if (act) {
-            const uint64_t na_ = xb[nxt * NPL];
-            const uint64_t nb_ = (MODEL == kTwoLane) ? xb[nxt * NPL + 1] : 0;
 #pragma unroll
             for (int i = 0; i < C; ++i) {
                 if (i < cnt) {

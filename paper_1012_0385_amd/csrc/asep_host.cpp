@@ -271,8 +271,15 @@ static bool plan_whole(const Resolved& r, Plan* p) {
     for (uint32_t C : Cs) {
         if (!sweep_variant_compiled(C, r.model, pick_kernel(r, C).variant)) continue;
         const uint32_t maxb = sweep_block_limit(C, r.model);
-        const uint32_t Tr = (nw + C - 1) / C;
+        uint32_t Tr = (nw + C - 1) / C;
         if (Tr > maxb) continue;
+        // rings of at most one wave get a power-of-two lane count, so none
+        // straddles two waves and the kernel exchanges across lanes
+        if (Tr < 64) {
+            uint32_t t = 1;
+            while (t < Tr) t <<= 1;
+            Tr = t;
+        }
         uint32_t G = 1;
         if (r.P.rings_per_wg)
             G = std::min(r.P.rings_per_wg, R);
