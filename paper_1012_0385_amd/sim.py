@@ -7,7 +7,6 @@ step of the simulation runs in the HIP library.
 from __future__ import annotations
 
 import ctypes
-from dataclasses import dataclass
 
 import numpy as np
 
@@ -49,24 +48,36 @@ def make_params(L: int, samples: int = 1, *, model: int = B.ASEP_MODEL_RING,
     return P
 
 
-@dataclass
 class Rough:
-    """Measurements of one time: per-sample exact sums and W^2."""
+    """Measurements of one time: per-sample exact sums and W^2.
 
-    S1: np.ndarray     # int64 [samples]
-    S2: list           # python ints [samples]
-    J: np.ndarray      # int64 [samples]
-    N: np.ndarray      # int64 [samples]
-    w2: np.ndarray     # float64 [samples]
+    S1, J, N are int64 arrays, w2 float64; S2 (the 128-bit sum of squared
+    heights) is kept as its two 64-bit halves and formed as Python ints on
+    first use."""
+
+    __slots__ = ("S1", "S2_lo", "S2_hi", "J", "N", "w2", "_s2")
+
+    def __init__(self, S1, S2_lo, S2_hi, J, N, w2):
+        self.S1, self.S2_lo, self.S2_hi, self.J, self.N, self.w2 = S1, S2_lo, S2_hi, J, N, w2
+        self._s2 = None
+
+    @property
+    def S2(self) -> list:
+        if self._s2 is None:
+            self._s2 = [(int(h) << 64) + int(lo) for h, lo in zip(self.S2_hi, self.S2_lo)]
+        return self._s2
 
 
-def _rough_arrays(arr, n: int) -> Rough:
-    S1 = np.array([arr[i].sum_h for i in range(n)], dtype=np.int64)
-    S2 = [(int(arr[i].sum_h2_hi) << 64) + int(arr[i].sum_h2_lo) for i in range(n)]
-    J = np.array([arr[i].hops for i in range(n)], dtype=np.int64)
-    N = np.array([arr[i].particles for i in range(n)], dtype=np.int64)
-    w2 = np.array([arr[i].w2 for i in range(n)], dtype=np.float64)
-    return Rough(S1, S2, J, N, w2)
+_ROUGH_DTYPE = np.dtype([("sum_h", "<i8"), ("sum_h2_lo", "<u8"), ("sum_h2_hi", "<i8"),
+                         ("hops", "<i8"), ("particles", "<i8"), ("w2", "<f8")])
+
+
+def _rough_arrays(arr, n: int, first: int = 0) -> Rough:
+    """Rough of records first..first+n of a ctypes asep_rough array (copied out)."""
+    assert ctypes.sizeof(B.asep_rough) == _ROUGH_DTYPE.itemsize
+    a = np.frombuffer(arr, dtype=_ROUGH_DTYPE, count=n,
+                      offset=first * _ROUGH_DTYPE.itemsize).copy()
+    return Rough(a["sum_h"], a["sum_h2_lo"], a["sum_h2_hi"], a["hops"], a["particles"], a["w2"])
 
 
 class Simulation:
@@ -124,12 +135,7 @@ class Simulation:
         tarr = (ctypes.c_uint64 * max(n, 1))(*times)
         arr = (B.asep_rough * max(n * self.samples, 1))()
         B.check(B.load().asep_run(self._h, tarr, n, arr), "asep_run")
-        out = []
-        for i in range(n):
-            sub = (B.asep_rough * self.samples).from_address(
-                ctypes.addressof(arr) + i * self.samples * ctypes.sizeof(B.asep_rough))
-            out.append(_rough_arrays(sub, self.samples))
-        return out
+        return [_rough_arrays(arr, self.samples, i * self.samples) for i in range(n)]
 
     def read_state(self, sample: int) -> np.ndarray:
         n = self.planes * self.L // 64
@@ -209,12 +215,7 @@ def run_batch(sims, times) -> list:
     B.check(B.load().asep_run_batch(handles, len(sims), tarr, n, outs), "asep_run_batch")
     res = []
     for s, buf in zip(sims, bufs):
-        per = []
-        for i in range(n):
-            sub = (B.asep_rough * s.samples).from_address(
-                ctypes.addressof(buf) + i * s.samples * ctypes.sizeof(B.asep_rough))
-            per.append(_rough_arrays(sub, s.samples))
-        res.append(per)
+        res.append([_rough_arrays(buf, s.samples, i * s.samples) for i in range(n)])
     return res
 
 
@@ -232,8 +233,8 @@ def ensemble_w2(rough_list, L: int) -> float:
     arr = (B.asep_rough * n)()
     for i in range(n):
         arr[i].sum_h = int(rough_list.S1[i])
-        arr[i].sum_h2_lo = rough_list.S2[i] & ((1 << 64) - 1)
-        arr[i].sum_h2_hi = rough_list.S2[i] >> 64
+        arr[i].sum_h2_lo = int(rough_list.S2_lo[i])
+        arr[i].sum_h2_hi = int(rough_list.S2_hi[i])
     out = ctypes.c_double()
     B.check(B.load().asep_ensemble_w2(arr, n, L, ctypes.byref(out)), "asep_ensemble_w2")
     return out.value
