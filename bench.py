@@ -72,15 +72,35 @@ def sweep_traffic_bytes(shape):
     return (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024
 
 
+LDS_PEAK = 128 * 256 * 2.4e9  # B/clk/CU x CUs x clock
+
+
 def alu_slots_per_attempt(sim):
-    """Algorithmic 32-bit VALU slots per attempt for a simulation's schedule."""
+    """Algorithmic 32-bit VALU slots per attempt for a simulation under the
+    shifted schedule (None for the sub-lattice schedules, whose random bits
+    per update depend on the state through the lazy comparison)."""
     p = sim.params
+    if p.schedule != 0:
+        return None
+    two = p.model == 1
     ell = 1 << p.cell_log2
-    a = ell // p.subsweeps
-    w = p.cell_log2 + p.rbits
+    a = (4 * ell if two else ell) // p.subsweeps
+    w = p.cell_log2 + (2 if two else 0) + p.rbits
     per_word = 32 // w
     nblk = -(-a // (4 * per_word))
     return PHILOX_SLOTS * nblk / a + UPDATE_SLOTS
+
+
+def lds_bytes_per_attempt(sim):
+    """State bytes per attempt if the ring were read and written through LDS
+    once per sub-sweep (the LDS roofline's algorithmic traffic): L/4 bytes per
+    ring per sub-sweep (two lanes: twice that) plus L/8 per read-only mask
+    plane, over the attempts of a sub-sweep."""
+    p = sim.params
+    two = p.model == 1
+    per_sub = p.L / 4 * (2 if two else 1) + p.L / 8 * (1 if (p.slow_frac > 0 or two) else 0)
+    attempts_per_sub = p.L * (4 if two else 1) / p.subsweeps
+    return per_sub / attempts_per_sub
 
 
 def cpu_baseline(times_all, n_rings, t_cut):
@@ -103,9 +123,22 @@ def cpu_baseline(times_all, n_rings, t_cut):
         list(ex.map(lambda j: oracle.run(j[0], j[1], times), jobs))
     dt = time.perf_counter() - t0
     attempts = len(jobs) * L * t_cut
-    return {"value": attempts / dt, "unit": "site-updates/s", "cores": threads, "kind": "oracle",
-            "sample": "%d rings (KPZ and EW, %d each) of L=2^17 for the first %d of 10^5 MCS "
-                      "with the same measurement times; %.1f s wall" % (len(jobs), n_rings, t_cut, dt)}
+    out = {"value": attempts / dt, "unit": "site-updates/s", "cores": threads, "kind": "oracle",
+           "sample": "%d rings (KPZ and EW, %d each) of L=2^17 for the first %d of 10^5 MCS "
+                     "with the same measurement times; %.1f s wall" % (len(jobs), n_rings, t_cut, dt)}
+    # one core: one KPZ ring of the same prefix, and the L = 4096 job in full
+    t0 = time.perf_counter()
+    oracle.run(jobs[0][0], 0, times)
+    d1 = time.perf_counter() - t0
+    P1 = oracle.Params(L=4096, p=1.0, q=0.0, seed=1, stream=1)
+    t1 = [0] + [2 ** k for k in range(10)] + [1000]
+    t0 = time.perf_counter()
+    for i in range(8):
+        oracle.run(P1, i, t1)
+    d2 = time.perf_counter() - t0
+    out["single_core"] = {"value": L * t_cut / d1, "sample": "1 KPZ ring of L=2^17, %d MCS" % t_cut,
+                          "small_L4096_full": {"value": 8 * 4096 * 1000 / d2, "seconds": d2}}
+    return out
 
 
 def served_mix_leg(A, W, n_req, load, seed=5):
@@ -177,50 +210,94 @@ def served_mix_leg(A, W, n_req, load, seed=5):
     }
 
 
-def other_workloads(A, t_cut=1000):
-    """Site-updates/s of the other workload shapes (one timed run each after a
-    warm-up; prefixes of the long ones, with their measurement times)."""
+def other_workloads(A, t_cut=1000, t_span=2000):
+    """Site-updates/s of the other workload shapes, one timed run each after
+    a warm-up.  Jobs longer than t_cut MCS are timed twice: over their first
+    t_cut MCS ("prefix", with its dense measurement times) and over t_span
+    MCS from the middle of the job ("steady": the clock set to t_max/2, the
+    job's own measurement times in that span), which is what the bulk of the
+    job runs at.  `value` is the steady rate where there is one."""
     import torch
 
     from paper_1012_0385_amd import tune
 
     out = {}
     cases = [
-        ("small_L4096", dict(L=4096, p=1.0, q=0.0, seed=1, stream=1), 8,
+        ("small_L4096", dict(L=4096, p=1.0, q=0.0, seed=1, stream=1), 8, 1000,
          [0] + [2 ** k for k in range(10)] + [1000], "8 rings of 4096 sites, KPZ, 1000 MCS (full)"),
         ("disorder_L2p16", dict(L=1 << 16, p=1.0, q=0.0, slow_frac=0.1, slow_factor=0.5,
-                                samples_per_disorder=4, seed=1, stream=2), 4096, None,
-         "1024 disorder realisations x 4 noise, L=2^16, first %d of 10^6 MCS" % t_cut),
+                                samples_per_disorder=4, seed=1, stream=2), 4096, 10 ** 6, None,
+         "1024 disorder realisations x 4 noise, L=2^16, 10^6 MCS"),
         ("two_lane_L2p16", dict(L=1 << 16, model=1, init=1, density=0.3, p=1.0, q=1.0,
-                                lane_rate=0.1, turn_frac=0.05, seed=1, stream=3), 1024, None,
-         "1024 two-lane rings of 2^16 per lane, first %d of 10^5 MCS" % t_cut),
-        ("sca_L2p17", dict(L=1 << 17, p=0.8, q=0.0, seed=1, stream=4, schedule=1), 64, None,
-         "64 rings of 2^17, the paper's two-sub-lattice update at p = 0.8, first %d MCS" % t_cut),
+                                lane_rate=0.1, turn_frac=0.05, seed=1, stream=3), 1024, 10 ** 5,
+         None, "1024 two-lane rings of 2^16 per lane, 10^5 MCS"),
+        ("sca_L2p17", dict(L=1 << 17, p=0.8, q=0.0, seed=1, stream=4, schedule=1), 64, 10 ** 5,
+         None, "64 rings of 2^17, the paper's two-sub-lattice update at p = 0.8, 10^5 MCS"),
         ("qssep_sca_L2p15", dict(L=1 << 15, p=0.5, q=0.5, slow_frac=0.5, slow_factor=0.2, seed=1,
-                                 stream=5, schedule=1), 120, None,
+                                 stream=5, schedule=1), 120, 10 ** 6, None,
          "Q-SSEP (Q = 0.5, r = 0.2, p = q = 0.5), 120 realisations of 2^15, two-sub-lattice "
-         "update, first %d MCS" % t_cut),
+         "update, 10^6 MCS"),
         ("two_lane_sca_L2p12", dict(L=1 << 12, model=1, init=1, density=0.5, p=0.5, q=0.5,
                                     lane_rate=0.8, slow_frac=0.5, slow_factor=0.25, seed=1,
-                                    stream=6, schedule=1), 1024, None,
+                                    stream=6, schedule=1), 1024, 10 ** 5, None,
          "the paper's two-lane SCA sequence (in-lane 0.5, crossing 0.8 / 0.2 bimodal), "
-         "1024 rings of 2^12 per lane, first %d MCS" % t_cut),
+         "1024 rings of 2^12 per lane, 10^5 MCS"),
     ]
-    for name, kw, samples, times, desc in cases:
-        if times is None:
-            times = A.sample_times(30, 1.05, t_cut)
-            if times[-1] != t_cut:
-                times.append(t_cut)
-        sim = A.Simulation(A.make_params(samples=samples, **kw, **tune.lookup(kw, samples)))
-        sim.run(times[:3])
+
+    def timed_run(sim, times, t_start):
         sim.reset()
+        if t_start:
+            sim.set_time(t_start)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         sim.run(times)
         torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        work = samples * kw["L"] * (4 if kw.get("model", 0) == 1 else 1) * times[-1]
-        out[name] = {"value": work / dt, "unit": "site-updates/s", "seconds": dt, "workload": desc}
+        return time.perf_counter() - t0
+
+    for name, kw, samples, t_max, times, desc in cases:
+        full = A.sample_times(30, 1.05, t_max)
+        if full[-1] != t_max:
+            full.append(t_max)
+        per_mcs = samples * kw["L"] * (4 if kw.get("model", 0) == 1 else 1)
+        sim = A.Simulation(A.make_params(samples=samples, **kw, **tune.lookup(kw, samples)))
+        sim.run(full[:3])  # warm-up
+        entry = {"unit": "site-updates/s", "workload": desc}
+        if times is not None:  # whole job
+            dt = timed_run(sim, times, 0)
+            entry.update(value=per_mcs * times[-1] / dt, seconds=dt)
+            # the same rings one per run (each ring its own launch sequence)
+            singles = [A.Simulation(A.make_params(samples=1, sample_offset=i, **kw))
+                       for i in range(samples)]
+            for one in singles:
+                one.run(times[:2])
+                one.reset()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for one in singles:
+                one.run(times)
+            torch.cuda.synchronize()
+            d1 = time.perf_counter() - t0
+            entry["one_ring_per_run"] = {"value": per_mcs * times[-1] / d1, "seconds": d1}
+            for one in singles:
+                one.close()
+        else:
+            pre = [t for t in full if t <= t_cut] + ([t_cut] if t_cut not in full else [])
+            dt = timed_run(sim, pre, 0)
+            entry["prefix"] = {"value": per_mcs * t_cut / dt, "seconds": dt,
+                               "mcs": [0, t_cut], "measurements": len(pre)}
+            a = t_max // 2
+            span = [a] + [t for t in full if a < t < a + t_span] + [a + t_span]
+            dt = timed_run(sim, span, a)
+            entry["steady"] = {"value": per_mcs * t_span / dt, "seconds": dt,
+                               "mcs": [a, a + t_span], "measurements": len(span)}
+            entry["value"] = entry["steady"]["value"]
+        slots = alu_slots_per_attempt(sim)
+        if slots is not None:
+            # whole-run rate (launch gaps and measurements included) against
+            # the VALU peak: a lower bound of the kernel's own fraction
+            entry["alu_frac"] = entry["value"] * slots / PEAK_SLOTS
+            entry["slots_per_attempt"] = slots
+        out[name] = entry
         sim.close()
     return out
 
@@ -228,8 +305,8 @@ def other_workloads(A, t_cut=1000):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--cpu-rings", type=int, default=16)
     ap.add_argument("--cpu-mcs", type=int, default=1000)
@@ -292,13 +369,24 @@ def main():
             s.reset()
         return A.run_batch(sims, times)
 
-    def timed(step, n):
+    step_s = {"plain": [], "batched": []}
+
+    def timed(step, n, form):
+        # every step returns its records, i.e. ends synchronised with the device
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(n):
+            ts = time.perf_counter()
             step()
+            step_s[form].append(time.perf_counter() - ts)
         torch.cuda.synchronize()
         return time.perf_counter() - t0
+
+    def step_stats(form):
+        v = sorted(step_s[form])
+        if not v:
+            return None
+        return {"median_ms": v[len(v) // 2] * 1e3, "min_ms": v[0] * 1e3, "max_ms": v[-1] * 1e3}
 
     for _ in range(args.warmup):
         step_batched() if args.form == "both" else step_plain()
@@ -306,12 +394,12 @@ def main():
     # overlap, so each event pair times one kernel alone
     for s in sims:
         s.profile(True)
-    t_plain = timed(step_plain, args.steps)
+    t_plain = timed(step_plain, args.steps, "plain")
     prof = [s.profile_read() for s in sims]
     for s in sims:
         s.profile(False)
     # batched form
-    t_batch = timed(step_batched, args.steps) if args.form == "both" else t_plain
+    t_batch = timed(step_batched, args.steps, "batched") if args.form == "both" else t_plain
     print("plain %.3f s, batched %.3f s over %d steps" % (t_plain, t_batch, args.steps),
           file=sys.stderr)
 
@@ -327,6 +415,14 @@ def main():
                 "unit": "TOP/s", "frac": achieved / PEAK_SLOTS,
                 "traffic": sweep_traffic_bytes(shapes[0]),
                 "kernel": "k_sweep", "avg_launch_ms": avg_ms, "launches": launches}
+
+    # the LDS roofline as the workload statement defines it: the state through
+    # LDS once per sub-sweep; here the rings stay in VGPRs and LDS carries one
+    # neighbour word per lane and sub-sweep, so this fraction stays small
+    lds_bpa = lds_bytes_per_attempt(sims[0])
+    lds = {"bytes_per_attempt": lds_bpa, "achieved_GBps": value * lds_bpa / 1e9,
+           "peak_GBps": LDS_PEAK / 1e9, "frac": value * lds_bpa / LDS_PEAK,
+           "note": "state held in VGPRs; LDS carries 8 B per lane per sub-sweep"}
 
     others = None if args.no_others else other_workloads(A)
     if others:
@@ -362,9 +458,12 @@ def main():
                    "rings": len(sims) * SAMPLES, "L": L, "t_max": args.t_max,
                    "launch_shape": shapes[0] or "automatic",
                    "measurements": len(times), "parallelism": "1 GPU"},
-        "plain": {"value": plain_value, "ms_per_step": t_plain / args.steps * 1e3},
-        "batched": ({"value": batched_value, "ms_per_step": t_batch / args.steps * 1e3}
+        "plain": {"value": plain_value, "ms_per_step": t_plain / args.steps * 1e3,
+                  "steps": step_stats("plain")},
+        "batched": ({"value": batched_value, "ms_per_step": t_batch / args.steps * 1e3,
+                     "steps": step_stats("batched")}
                     if args.form == "both" else None),
+        "lds_roofline": lds,
         "roofline": roofline,
         "served_mix": mix,
         "other_workloads": others,
