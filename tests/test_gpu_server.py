@@ -73,6 +73,30 @@ def test_packed_small_requests_equal_alone():
     srv.close()
 
 
+def test_sublattice_requests_in_the_mix():
+    # the paper's SCA schedules (rings and two lanes) next to shifted ones:
+    # packed where shapes agree, every request equal to its run alone
+    reqs = []
+    for i in range(18):
+        if i % 3 == 0:
+            kw = dict(L=1024 + 64 * (i % 2), p=0.8, q=0.1 * (i % 2), seed=3 + i, stream=i,
+                      schedule=1)
+        elif i % 3 == 1:
+            kw = dict(L=512 * (1 + i % 2), model=1, init=1, p=0.5, q=0.5, lane_rate=0.8,
+                      slow_frac=0.5, slow_factor=0.25, seed=3 + i, stream=i, schedule=1)
+        else:
+            kw = dict(L=1024, p=1.0, q=0.0, seed=3 + i, stream=i)
+        reqs.append((kw, 1 + i % 3, [0, 2, 9, 25 + i]))
+    srv = A.Server(quantum_mcs=6, max_active=32)
+    tickets = [srv.submit(A.make_params(samples=n, **kw), times, times[-1]) for kw, n, times in reqs]
+    for (kw, n, times), t in zip(reqs, tickets):
+        res = srv.wait(t, timeout_s=120)
+        assert res["status"] == 0
+        for x, y in zip(res["rough"], alone(kw, n, times)):
+            assert same(x, y), kw
+    srv.close()
+
+
 def test_server_matches_oracle_small(orc):
     kw = dict(L=4096, p=1.0, q=0.0, seed=1, stream=1)
     times = [0, 1, 2, 4, 8, 16, 33]
