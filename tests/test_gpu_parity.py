@@ -276,3 +276,33 @@ def test_invalid_parameters_rejected():
         h = ctypes.c_void_p()
         assert lib.asep_create(ctypes.byref(P), ctypes.byref(h)) < 0
         assert not h.value
+
+
+def _records_and_states(kw, times, samples):
+    sim = A.Simulation(A.make_params(samples=samples, **kw))
+    rec = sim.run(times)
+    states = [sim.read_state(i) for i in range(samples)]
+    sim.close()
+    return rec, states
+
+
+@pytest.mark.parametrize("base", [
+    dict(L=8192, p=0.75, q=0.25, init=1, seed=4, stream=4),
+    dict(L=8192, p=0.8, q=0.1, init=1, seed=4, stream=5, schedule=1),
+    dict(L=4096, model=1, init=1, p=0.5, q=0.5, lane_rate=0.8, slow_frac=0.5, slow_factor=0.25,
+         seed=4, stream=6, schedule=1),
+])
+def test_launch_shape_invariance(base):
+    # rings per workgroup, whole rings vs windows of several sizes and reaches:
+    # launch shape only, so every record and every final word is identical
+    times = [0, 3, 10, 31]
+    ref, ref_states = _records_and_states(dict(base, windows=1, rings_per_wg=1), times, 6)
+    for shape in [dict(windows=1, rings_per_wg=2), dict(windows=1, rings_per_wg=6),
+                  dict(windows=2, window_sweeps=5), dict(windows=3, window_sweeps=13),
+                  dict(windows=4, window_sweeps=2)]:
+        got, states = _records_and_states(dict(base, **shape), times, 6)
+        for x, y in zip(got, ref):
+            assert np.array_equal(x.S1, y.S1) and x.S2 == y.S2, shape
+            assert np.array_equal(x.J, y.J) and np.array_equal(x.N, y.N), shape
+        for a, b in zip(states, ref_states):
+            assert np.array_equal(a, b), shape
