@@ -33,8 +33,14 @@ SAMPLES = 64
 T_MAX = 100_000
 MODELS = (("kpz", 1.0, 0.0, 0), ("ew", 0.5, 0.5, 1))  # name, p, q, stream id
 PEAK_SLOTS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock: 32-bit VALU slots/s
-PHILOX_SLOTS = 100  # 10 rounds x (2 quarter-rate 32x32->64 products + 2 xor3)
-UPDATE_SLOTS = 10   # field extraction, pair test, thresholds, flip, hop count
+# Algorithmic VALU work, in full-rate lane slots: a Philox4x32-10 block is 10
+# rounds x (2 32x32->64 products + 2 three-input XORs), each product one
+# v_mad_u64_u32 and each XOR one v_bitop3_b32, counted as one slot apiece
+# (a throughput probe puts the product at ~1.35 slots on gfx950, so this
+# count is the conservative one); an attempt's update is field extraction,
+# pair test, threshold, flip and hop count.
+PHILOX_SLOTS = 40
+UPDATE_SLOTS = 10
 
 # HBM traffic of one sweep launch at the tuned launch shape: rocprofv3 --pmc
 # FETCH_SIZE and WRITE_SIZE (KiB per dispatch, mean over the sweep dispatches
@@ -220,29 +226,9 @@ def other_workloads(A, t_cut=1000, t_span=2000):
     import torch
 
     from paper_1012_0385_amd import tune
+    from paper_1012_0385_amd import workloads as W
 
     out = {}
-    cases = [
-        ("small_L4096", dict(L=4096, p=1.0, q=0.0, seed=1, stream=1), 8, 1000,
-         [0] + [2 ** k for k in range(10)] + [1000], "8 rings of 4096 sites, KPZ, 1000 MCS (full)"),
-        ("disorder_L2p16", dict(L=1 << 16, p=1.0, q=0.0, slow_frac=0.1, slow_factor=0.5,
-                                samples_per_disorder=4, seed=1, stream=2), 4096, 10 ** 6, None,
-         "1024 disorder realisations x 4 noise, L=2^16, 10^6 MCS"),
-        ("two_lane_L2p16", dict(L=1 << 16, model=1, init=1, density=0.3, p=1.0, q=1.0,
-                                lane_rate=0.1, turn_frac=0.05, seed=1, stream=3), 1024, 10 ** 5,
-         None, "1024 two-lane rings of 2^16 per lane, 10^5 MCS"),
-        ("sca_L2p17", dict(L=1 << 17, p=0.8, q=0.0, seed=1, stream=4, schedule=1), 64, 10 ** 5,
-         None, "64 rings of 2^17, the paper's two-sub-lattice update at p = 0.8, 10^5 MCS"),
-        ("qssep_sca_L2p15", dict(L=1 << 15, p=0.5, q=0.5, slow_frac=0.5, slow_factor=0.2, seed=1,
-                                 stream=5, schedule=1), 120, 10 ** 6, None,
-         "Q-SSEP (Q = 0.5, r = 0.2, p = q = 0.5), 120 realisations of 2^15, two-sub-lattice "
-         "update, 10^6 MCS"),
-        ("two_lane_sca_L2p12", dict(L=1 << 12, model=1, init=1, density=0.5, p=0.5, q=0.5,
-                                    lane_rate=0.8, slow_frac=0.5, slow_factor=0.25, seed=1,
-                                    stream=6, schedule=1), 1024, 10 ** 5, None,
-         "the paper's two-lane SCA sequence (in-lane 0.5, crossing 0.8 / 0.2 bimodal), "
-         "1024 rings of 2^12 per lane, 10^5 MCS"),
-    ]
 
     def timed_run(sim, times, t_start):
         sim.reset()
@@ -254,7 +240,7 @@ def other_workloads(A, t_cut=1000, t_span=2000):
         torch.cuda.synchronize()
         return time.perf_counter() - t0
 
-    for name, kw, samples, t_max, times, desc in cases:
+    for name, (kw, samples, t_max, times, desc) in W.WORKLOADS.items():
         full = A.sample_times(30, 1.05, t_max)
         if full[-1] != t_max:
             full.append(t_max)

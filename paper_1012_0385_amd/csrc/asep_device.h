@@ -28,16 +28,36 @@ struct Blk {
     uint32_t v[4];
 };
 
+// a ^ b ^ k in one VALU instruction (gfx950's three-input bitwise op with
+// the XOR truth table 0x96), k wave-uniform (an SGPR operand).
+__device__ __forceinline__ uint32_t xor3_uniform(uint32_t a, uint32_t b, uint32_t k) {
+    uint32_t r;
+    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "s"(k), "v"(b));
+    return r;
+}
+
 // Ten Philox rounds: products of counter words 0 and 2, high halves mixed
-// with the other two words and the round key, Weyl key schedule.
+// with the other two words and the round key, Weyl key schedule.  The key
+// must be wave-uniform.  With FUSE, from the third round on (where every
+// counter word varies across lanes) each mix is one three-input XOR; the
+// first two rounds are left to the compiler, which keeps their uniform parts
+// scalar.  FUSE is off where the compiler's own schedule measured faster
+// (the attempt loop with quenched-rate lookups).
+template <bool FUSE = true>
 __device__ __forceinline__ Blk philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                       uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int i = 0; i < 10; ++i) {
         const uint64_t pa = (uint64_t)kMulA * (uint64_t)c0;
         const uint64_t pb = (uint64_t)kMulB * (uint64_t)c2;
-        const uint32_t n0 = (uint32_t)(pb >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(pa >> 32) ^ c3 ^ k1;
+        uint32_t n0, n2;
+        if (FUSE && i >= 2) {
+            n0 = xor3_uniform((uint32_t)(pb >> 32), c1, k0);
+            n2 = xor3_uniform((uint32_t)(pa >> 32), c3, k1);
+        } else {
+            n0 = (uint32_t)(pb >> 32) ^ c1 ^ k0;
+            n2 = (uint32_t)(pa >> 32) ^ c3 ^ k1;
+        }
         c1 = (uint32_t)pb;
         c3 = (uint32_t)pa;
         c0 = n0;
@@ -130,7 +150,7 @@ __device__ __forceinline__ int32_t cell_ring_generic(uint64_t& x, uint64_t m0, u
     int32_t dj = 0;
     uint32_t m = 0;
     for (uint32_t blk = 0; blk < c.nblk; ++blk) {
-        const Blk r = philox(c.k, c.glo, c.c2b | (blk << 16), c.sample, c.k0, c.k1);
+        const Blk r = philox<!DIS>(c.k, c.glo, c.c2b | (blk << 16), c.sample, c.k0, c.k1);
 #pragma unroll
         for (int wd = 0; wd < 4; ++wd) {
             const uint32_t u = r.v[wd];
@@ -172,7 +192,8 @@ __device__ __forceinline__ int32_t cell_ring_fast(uint64_t& x, uint64_t m0, uint
     int32_t dj = 0;
 #pragma unroll
     for (int blk = 0; blk < NB; ++blk) {
-        const Blk r = philox(c.k, c.glo, c.c2b | ((uint32_t)blk << 16), c.sample, c.k0, c.k1);
+        const Blk r =
+            philox<!DIS>(c.k, c.glo, c.c2b | ((uint32_t)blk << 16), c.sample, c.k0, c.k1);
 #pragma unroll
         for (int wd = 0; wd < 4; ++wd) {
 #pragma unroll

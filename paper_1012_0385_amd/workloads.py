@@ -20,6 +20,33 @@ MODELS = {
 }
 
 
+# Named ensemble workloads (besides the L = 2^17 KPZ + EW pair of the headline
+# benchmark): (run parameters, samples, t_max, explicit times or None for the
+# geometric schedule, description).
+WORKLOADS = {
+    "small_L4096": (dict(L=4096, p=1.0, q=0.0, seed=1, stream=1), 8, 1000,
+                    [0] + [2 ** k for k in range(10)] + [1000],
+                    "8 rings of 4096 sites, KPZ, 1000 MCS (full)"),
+    "disorder_L2p16": (dict(L=1 << 16, p=1.0, q=0.0, slow_frac=0.1, slow_factor=0.5,
+                            samples_per_disorder=4, seed=1, stream=2), 4096, 10 ** 6, None,
+                       "1024 disorder realisations x 4 noise, L=2^16, 10^6 MCS"),
+    "two_lane_L2p16": (dict(L=1 << 16, model=1, init=1, density=0.3, p=1.0, q=1.0, lane_rate=0.1,
+                            turn_frac=0.05, seed=1, stream=3), 1024, 10 ** 5, None,
+                       "1024 two-lane rings of 2^16 per lane, 10^5 MCS"),
+    "sca_L2p17": (dict(L=1 << 17, p=0.8, q=0.0, seed=1, stream=4, schedule=1), 64, 10 ** 5, None,
+                  "64 rings of 2^17, the paper's two-sub-lattice update at p = 0.8, 10^5 MCS"),
+    "qssep_sca_L2p15": (dict(L=1 << 15, p=0.5, q=0.5, slow_frac=0.5, slow_factor=0.2, seed=1,
+                             stream=5, schedule=1), 120, 10 ** 6, None,
+                        "Q-SSEP (Q = 0.5, r = 0.2, p = q = 0.5), 120 realisations of 2^15, "
+                        "two-sub-lattice update, 10^6 MCS"),
+    "two_lane_sca_L2p12": (dict(L=1 << 12, model=1, init=1, density=0.5, p=0.5, q=0.5,
+                                lane_rate=0.8, slow_frac=0.5, slow_factor=0.25, seed=1, stream=6,
+                                schedule=1), 1024, 10 ** 5, None,
+                           "the paper's two-lane SCA sequence (in-lane 0.5, crossing 0.8 / 0.2 "
+                           "bimodal), 1024 rings of 2^12 per lane, 10^5 MCS"),
+}
+
+
 def geometric_times(t_max: int, t0: float = 30.0, factor: float = 1.05) -> list:
     """t = 0 and ceil(t0 * factor^i) <= t_max (Eq. sampling), plus t_max."""
     out = [0]
