@@ -339,6 +339,16 @@ __device__ __forceinline__ uint64_t unfold_pairs(uint32_t a) {
     return (uint64_t)(a & 0x55555555u) | ((uint64_t)((a >> 1) & 0x55555555u) << 32);
 }
 
+// One bit plane of a lazy bit-sliced comparison U < T from the top bit:
+// `t` marks the pairs (sites) whose threshold has a 1 at this bit, `u` holds
+// this bit of their U.  Pairs where u < t become accepted, pairs where they
+// differ leave the undecided set.
+template <typename W>
+__device__ __forceinline__ void cmp_plane(W& lt, W& und, W t, W u) {
+    lt |= und & t & ~u;
+    und &= ~(t ^ u);
+}
+
 template <bool Q0, bool DIS>
 __device__ __forceinline__ int32_t sca_slot(uint64_t& x, uint64_t m0, uint64_t m1,
                                             const CellCtx& c) {
@@ -355,54 +365,45 @@ __device__ __forceinline__ int32_t sca_slot(uint64_t& x, uint64_t m0, uint64_t m
     const uint32_t full = 1u << c.b;
     uint32_t acc = 0, und = 0;
     uint32_t depth[4];  // leading bits that decide a comparison with thr[i]
+    uint32_t ta[4];     // thresholds left-aligned: plane n reads bit 31 - n
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         depth[i] = 0;
+        ta[i] = 0;
         if (thr[i] >= full) {
             acc |= cls[i];
         } else if (thr[i] != 0) {
             und |= cls[i];
             depth[i] = c.b - (uint32_t)__builtin_ctz(thr[i]);
+            ta[i] = thr[i] << (32u - c.b);  // 1 <= b <= 24 here
         }
     }
+    // Planes past a class's depth carry threshold bit 0, so its pairs can
+    // only leave the undecided set there (as rejections); cutting the class
+    // at the end of the block that reaches its depth decides the same.
     uint32_t lt = 0;
     for (uint32_t blk = 0; und != 0u && blk < c.nblk; ++blk) {
         const Blk rb = philox(c.k, c.glo, c.c2b | (blk << 16), c.sample, c.k0, c.k1);
 #pragma unroll
         for (int wd = 0; wd < 4; ++wd) {
-            const uint32_t n = blk * 4u + (uint32_t)wd;
-            if (n < c.b) {
-                const uint32_t kb = c.b - 1u - n;
-                uint32_t t = 0;
+            const uint32_t sh = 31u - (blk * 4u + (uint32_t)wd);  // >= 8: at most 6 blocks
+            uint32_t t = 0;
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    if (!(Q0 && (i & 1)) && (DIS || i < 2))
-                        t |= cls[i] & (0u - ((thr[i] >> kb) & 1u));
-                const uint32_t u = rb.v[wd];
-                lt |= und & t & ~u;
-                und &= ~(t ^ u);
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    if (!(Q0 && (i & 1)) && (DIS || i < 2))
-                        if (n + 1u == depth[i]) und &= ~cls[i];
-            }
+            for (int i = 0; i < 4; ++i)
+                if (!(Q0 && (i & 1)) && (DIS || i < 2))
+                    t |= cls[i] & (0u - ((ta[i] >> sh) & 1u));
+            cmp_plane(lt, und, t, rb.v[wd]);
         }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (!(Q0 && (i & 1)) && (DIS || i < 2))
+                if (4u * (blk + 1u) >= depth[i]) und &= ~cls[i];
     }
     acc |= lt;
     const uint64_t a64 = unfold_pairs(acc);
     x ^= a64 | (a64 << 1);
     if (Q0) return __popc(acc);
     return __popc(acc & fw) - __popc(acc & bw);
-}
-
-// One bit plane of a lazy bit-sliced comparison U < T from the top bit:
-// `t` marks the pairs (sites) whose threshold has a 1 at this bit, `u` holds
-// this bit of their U.  Pairs where u < t become accepted, pairs where they
-// differ leave the undecided set.
-template <typename W>
-__device__ __forceinline__ void cmp_plane(W& lt, W& und, W t, W u) {
-    lt |= und & t & ~u;
-    und &= ~(t ^ u);
 }
 
 // Accept-all / undecided split of one threshold class, and the number of
@@ -432,19 +433,20 @@ __device__ __forceinline__ int32_t sca_two_inlane(uint64_t& xa, uint64_t& xb, co
     uint32_t acc_a = 0, acc_b = 0, und_a = 0, und_b = 0, lt_a = 0, lt_b = 0;
     const uint32_t da = sca_class(fa, c.T0, c.b, acc_a, und_a);
     const uint32_t db = sca_class(fb, c.T1, c.b, acc_b, und_b);
+    // left-aligned thresholds (plane n reads bit 31 - n; bits past b are 0),
+    // classes cut at the end of the block reaching their depth (as sca_slot)
+    const uint32_t ta0 = c.b ? c.T0 << (32u - c.b) : 0u;
+    const uint32_t ta1 = c.b ? c.T1 << (32u - c.b) : 0u;
     for (uint32_t blk = 0; (und_a | und_b) != 0u && blk < c.nblk; ++blk) {
         const Blk r = philox(c.k, c.glo, c.c2b | (blk << 16), c.sample, c.k0, c.k1);
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-            const uint32_t n = 2u * blk + (uint32_t)j;
-            if (n < c.b) {
-                const uint32_t kb = c.b - 1u - n;
-                cmp_plane(lt_a, und_a, fa & (0u - ((c.T0 >> kb) & 1u)), r.v[2 * j]);
-                cmp_plane(lt_b, und_b, fb & (0u - ((c.T1 >> kb) & 1u)), r.v[2 * j + 1]);
-                if (n + 1u == da) und_a = 0;
-                if (n + 1u == db) und_b = 0;
-            }
+            const uint32_t sh = 31u - (2u * blk + (uint32_t)j);  // >= 8: at most 12 blocks
+            cmp_plane(lt_a, und_a, fa & (0u - ((ta0 >> sh) & 1u)), r.v[2 * j]);
+            cmp_plane(lt_b, und_b, fb & (0u - ((ta1 >> sh) & 1u)), r.v[2 * j + 1]);
         }
+        if (2u * (blk + 1u) >= da) und_a = 0;
+        if (2u * (blk + 1u) >= db) und_b = 0;
     }
     acc_a |= lt_a;
     acc_b |= lt_b;
@@ -465,21 +467,20 @@ __device__ __forceinline__ void sca_two_change(uint64_t& from, uint64_t& to, uin
     uint64_t acc = 0, und = 0, lt = 0;
     const uint32_t d0 = sca_class(c0, c.T2, c.b, acc, und);
     const uint32_t d1 = sca_class(c1, c.T3, c.b, acc, und);
+    const uint32_t ta2 = c.b ? c.T2 << (32u - c.b) : 0u;
+    const uint32_t ta3 = c.b ? c.T3 << (32u - c.b) : 0u;
     for (uint32_t blk = 0; und != 0u && blk < c.nblk; ++blk) {
         const Blk r = philox(c.k, c.glo, c.c2b | (blk << 16), c.sample, c.k0, c.k1);
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-            const uint32_t n = 2u * blk + (uint32_t)j;
-            if (n < c.b) {
-                const uint32_t kb = c.b - 1u - n;
-                const uint64_t u = (uint64_t)r.v[2 * j] | ((uint64_t)r.v[2 * j + 1] << 32);
-                const uint64_t t = (c0 & (0ull - ((c.T2 >> kb) & 1u))) |
-                                   (c1 & (0ull - ((c.T3 >> kb) & 1u)));
-                cmp_plane(lt, und, t, u);
-                if (n + 1u == d0) und &= ~c0;
-                if (n + 1u == d1) und &= ~c1;
-            }
+            const uint32_t sh = 31u - (2u * blk + (uint32_t)j);
+            const uint64_t u = (uint64_t)r.v[2 * j] | ((uint64_t)r.v[2 * j + 1] << 32);
+            const uint64_t t = (c0 & (0ull - ((ta2 >> sh) & 1u))) |
+                               (c1 & (0ull - ((ta3 >> sh) & 1u)));
+            cmp_plane(lt, und, t, u);
         }
+        if (2u * (blk + 1u) >= d0) und &= ~c0;
+        if (2u * (blk + 1u) >= d1) und &= ~c1;
     }
     const uint64_t flip = acc | lt;
     from ^= flip;
