@@ -776,9 +776,19 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
 #pragma unroll
         for (int i = 0; i < C; ++i)
             if (i < cnt) dl += 64 - 2 * (int32_t)__popcll(sa[i]);
+        // inclusive prefix sum of the height steps over the workgroup: within
+        // each wave by lane permutes (every lane takes part), then the wave
+        // totals through LDS
+        const uint32_t lane = tid & 63u, wv = tid >> 6;
+        int32_t v = dl;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int32_t up = __shfl_up(v, (unsigned)d, 64);
+            if (lane >= (uint32_t)d) v += up;
+        }
         int32_t* s0p = scan;
-        int32_t* s1p = scan + block;
-        s0p[tid] = dl;
+        int32_t* wsum = scan + block;
+        if (lane == 63u) wsum[wv] = v;
         if (lt == 0 && gi < G) {
             red[gi * 4 + 0] = 0;
             red[gi * 4 + 1] = 0;
@@ -786,15 +796,9 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
             red[gi * 4 + 3] = 0;
         }
         __syncthreads();
-        for (uint32_t d = 1; d < block; d <<= 1) {
-            const int32_t v = s0p[tid] + (tid >= d ? s0p[tid - d] : 0);
-            __syncthreads();
-            s1p[tid] = v;
-            __syncthreads();
-            int32_t* t = s0p;
-            s0p = s1p;
-            s1p = t;
-        }
+        for (uint32_t w = 0; w < wv; ++w) v += wsum[w];
+        s0p[tid] = v;
+        __syncthreads();
         const int32_t before = (lane0 > 0) ? s0p[lane0 - 1] : 0;
         const int32_t excl = s0p[tid] - dl - before;
         const int32_t last = lane0 + Tr - 1 < block ? lane0 + Tr - 1 : block - 1;
