@@ -137,6 +137,10 @@ struct CellCtx {
     uint32_t T0, T1, T2, T3;
     uint32_t lut;     // packed 8-bit thresholds {0, T0, T1, 0} for pair 0..3
     uint32_t lut3;    // packed flips {0, 3 T0, 3 T1, 0} (thresholds of 0 bits)
+    // With 1 or 2 compared bits: outcome of pair pr with compared bits rv in
+    // the 2-bit field at bit 8 pr + rv (8 >> b): lutF the flip (0 or 3),
+    // lutD the hop plus one (0 left, 1 none, 2 right).
+    uint32_t lutF, lutD;
 };
 
 // Generic single-lane cell: any cell size ell <= 64 located at bit `bb` of
@@ -209,6 +213,13 @@ __device__ __forceinline__ int32_t cell_ring_fast(uint64_t& x, uint64_t m0, uint
                 if (BB == 0 && !DIS) {
                     // the field offset of v_bfe_u32 is taken mod 32: (sx << 3) mod 32 = 8 pr
                     f = bfe(c.lut3, (uint32_t)sx << 3, 8);
+                } else if ((BB == 1 || BB == 2) && !DIS) {
+                    // pair and compared bits select the outcome in one table
+                    const uint32_t off = ((uint32_t)sx << 3) + (bfe(u, sh, BB) << (3 - BB));
+                    f = bfe(c.lutF, off, 2);
+                    x ^= (uint64_t)f << j;
+                    dj += (int32_t)(Q0 ? f : bfe(c.lutD, off, 2));
+                    continue;
                 } else {
                     const uint32_t rv = (BB == 0) ? 0u : bfe(u, sh, b);
                     uint32_t tsel;
@@ -232,6 +243,7 @@ __device__ __forceinline__ int32_t cell_ring_fast(uint64_t& x, uint64_t m0, uint
             }
         }
     }
+    if ((BB == 1 || BB == 2) && !DIS && !Q0) return dj - NA;  // hops were stored plus one
     return Q0 ? dj / 3 : dj;
 }
 
@@ -688,6 +700,18 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
     cc.T3 = P.sc.T[3];
     cc.lut = (P.sc.T[0] << 8) | (P.sc.T[1] << 16);
     cc.lut3 = ((3u * P.sc.T[0]) << 8) | ((3u * P.sc.T[1]) << 16);
+    cc.lutF = 0;
+    cc.lutD = 0;
+    if (P.sc.b == 1 || P.sc.b == 2) {
+        for (uint32_t pr = 0; pr < 4; ++pr)
+            for (uint32_t rv = 0; rv < (1u << P.sc.b); ++rv) {
+                const bool right = pr == 1u && rv < P.sc.T[0];
+                const bool left = pr == 2u && rv < P.sc.T[1];
+                const uint32_t at = 8u * pr + rv * (8u >> P.sc.b);
+                cc.lutF |= (right || left ? 3u : 0u) << at;
+                cc.lutD |= (right ? 2u : (left ? 0u : 1u)) << at;
+            }
+    }
 
     // load the window (whole ring: every word)
     uint64_t sa[C];
