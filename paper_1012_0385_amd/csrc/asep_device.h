@@ -36,6 +36,21 @@ __device__ __forceinline__ uint32_t xor3_uniform(uint32_t a, uint32_t b, uint32_
     return r;
 }
 
+// x ^ (m & f) in one VALU instruction (three-input bitwise op, truth table
+// 0x78 with the inputs in the order x, m, f).
+__device__ __forceinline__ uint32_t xor_masked(uint32_t x, uint32_t m, uint32_t f) {
+    uint32_t r;
+    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x78" : "=v"(r) : "v"(x), "v"(m), "v"(f));
+    return r;
+}
+
+// (a & 3) | (b & ~3): the low two bits of a below the rest of b.
+__device__ __forceinline__ uint32_t insert_low2(uint32_t a, uint32_t b) {
+    uint32_t r;
+    asm("v_bfi_b32 %0, 3, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
 // Ten Philox rounds: products of counter words 0 and 2, high halves mixed
 // with the other two words and the round key, Weyl key schedule.  The key
 // must be wave-uniform.  With FUSE, from the third round on (where every
@@ -136,11 +151,10 @@ struct CellCtx {
     uint32_t na, nblk, b, w, A;
     uint32_t T0, T1, T2, T3;
     uint32_t lut;     // packed 8-bit thresholds {0, T0, T1, 0} for pair 0..3
-    uint32_t lut3;    // packed flips {0, 3 T0, 3 T1, 0} (thresholds of 0 bits)
-    // With 1 or 2 compared bits: outcome of pair pr with compared bits rv in
-    // the 2-bit field at bit 8 pr + rv (8 >> b): lutF the flip (0 or 3),
-    // lutD the hop plus one (0 left, 1 none, 2 right).
-    uint32_t lutF, lutD;
+    // With at most 2 compared bits: bit o says whether pair o mod 4 with
+    // compared bits (o >> 2) mod 2^b hops (the pattern repeats every 2^(2+b)
+    // bits, so any higher bits of the offset select the same outcome).
+    uint32_t lutP;
 };
 
 // Generic single-lane cell: any cell size ell <= 64 located at bit `bb` of
@@ -185,9 +199,10 @@ __device__ __forceinline__ int32_t cell_ring_generic(uint64_t& x, uint64_t m0, u
 // at compile time (BB < 0: runtime).  The pair (x, x+1) is read with an
 // arithmetic shift: at j = 63 the top bit is replicated, the pair is 00 or
 // 11 and nothing can hop, which is exactly the no-op of the bond leaving the
-// cell.  With BB = 0 the acceptance is decided by the pair alone, so one
-// packed table gives the flip pattern (0 or 3) directly.  Q0: no backward
-// hops (q = 0): every flip is a right hop.
+// cell.  With at most two compared bits (p, q multiples of 1/4) the pair and
+// those bits index one 32-bit pattern of outcomes (lutP), and the hop is an
+// XOR with 3 << j under the all-ones-or-zero outcome.  Q0: no backward hops
+// (q = 0): every flip is a right hop.
 template <int A, int BB, bool Q0, bool DIS, int NA>
 __device__ __forceinline__ int32_t cell_ring_fast(uint64_t& x, uint64_t m0, uint64_t m1,
                                                    const CellCtx& c) {
@@ -210,15 +225,26 @@ __device__ __forceinline__ int32_t cell_ring_fast(uint64_t& x, uint64_t m0, uint
                 const int64_t sx = (int64_t)x >> j;
                 const uint32_t pr = (uint32_t)sx & 3u;
                 uint32_t f;
-                if (BB == 0 && !DIS) {
-                    // the field offset of v_bfe_u32 is taken mod 32: (sx << 3) mod 32 = 8 pr
-                    f = bfe(c.lut3, (uint32_t)sx << 3, 8);
-                } else if ((BB == 1 || BB == 2) && !DIS) {
-                    // pair and compared bits select the outcome in one table
-                    const uint32_t off = ((uint32_t)sx << 3) + (bfe(u, sh, BB) << (3 - BB));
-                    f = bfe(c.lutF, off, 2);
-                    x ^= (uint64_t)f << j;
-                    dj += (int32_t)(Q0 ? f : bfe(c.lutD, off, 2));
+                if (BB >= 0 && BB <= 2 && !DIS) {
+                    // Offset into lutP: the pair in bits 0-1, the compared
+                    // bits above it (v_bfe takes the offset mod 32, so the
+                    // sites beyond the pair only repeat the pattern).  F is
+                    // all ones when the pair hops; the flip mask 3 << j does
+                    // not wait for the state.
+                    uint32_t off = (uint32_t)sx;
+                    if (BB > 0) {
+                        const uint32_t rs = sh >= 2 ? u >> (sh - 2) : u << (2 - sh);
+                        off = insert_low2(off, rs);
+                    }
+                    const uint32_t F = (uint32_t)__builtin_amdgcn_sbfe((int32_t)c.lutP, off, 1);
+                    const uint64_t M = 3ull << j;
+                    const uint32_t lo = xor_masked((uint32_t)x, (uint32_t)M, F);
+                    const uint32_t hi = xor_masked((uint32_t)(x >> 32), (uint32_t)(M >> 32), F);
+                    x = ((uint64_t)hi << 32) | lo;
+                    // Q0: minus one per (right) hop; otherwise a hop adds
+                    // F = -1 plus 2 when site j+1 was empty, i.e. it went right
+                    dj += (int32_t)F;
+                    if (!Q0) dj += (int32_t)(F & ~(uint32_t)sx & 2u);
                     continue;
                 } else {
                     const uint32_t rv = (BB == 0) ? 0u : bfe(u, sh, b);
@@ -243,7 +269,7 @@ __device__ __forceinline__ int32_t cell_ring_fast(uint64_t& x, uint64_t m0, uint
             }
         }
     }
-    if ((BB == 1 || BB == 2) && !DIS && !Q0) return dj - NA;  // hops were stored plus one
+    if (BB >= 0 && BB <= 2 && !DIS) return Q0 ? -dj : dj;
     return Q0 ? dj / 3 : dj;
 }
 
@@ -699,18 +725,13 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
     cc.T2 = P.sc.T[2];
     cc.T3 = P.sc.T[3];
     cc.lut = (P.sc.T[0] << 8) | (P.sc.T[1] << 16);
-    cc.lut3 = ((3u * P.sc.T[0]) << 8) | ((3u * P.sc.T[1]) << 16);
-    cc.lutF = 0;
-    cc.lutD = 0;
-    if (P.sc.b == 1 || P.sc.b == 2) {
-        for (uint32_t pr = 0; pr < 4; ++pr)
-            for (uint32_t rv = 0; rv < (1u << P.sc.b); ++rv) {
-                const bool right = pr == 1u && rv < P.sc.T[0];
-                const bool left = pr == 2u && rv < P.sc.T[1];
-                const uint32_t at = 8u * pr + rv * (8u >> P.sc.b);
-                cc.lutF |= (right || left ? 3u : 0u) << at;
-                cc.lutD |= (right ? 2u : (left ? 0u : 1u)) << at;
-            }
+    cc.lutP = 0;
+    if (P.sc.b <= 2) {
+        for (uint32_t o = 0; o < 32; ++o) {
+            const uint32_t pr = o & 3u, rv = (o >> 2) & ((1u << P.sc.b) - 1u);
+            const bool hop = (pr == 1u && rv < P.sc.T[0]) || (pr == 2u && rv < P.sc.T[1]);
+            cc.lutP |= (hop ? 1u : 0u) << o;
+        }
     }
 
     // load the window (whole ring: every word)
@@ -745,6 +766,8 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
     // up to 64, so no ring straddles two waves) exchange across lanes
     const bool wsync = !seg && Tr <= 64u && (64u % Tr) == 0u;
     uint32_t sig = 0, off = 0, buf = 0;
+    // word held by this lane's slot 0: (base + off + base_slot) mod nw
+    uint32_t wb = (uint32_t)(((uint64_t)base + base_slot) % nw);
     int64_t J = 0;
     const int64_t hops0 = (ring_ok && !seg) ? P.hops[ring] : 0;
 
@@ -787,6 +810,7 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
         }
         if (wrap) {
             off += 1;
+            wb = (wb + 1 == nw) ? 0u : wb + 1;
             if (!seg && off == nw) off = 0;
         }
         sig = sig_new;
@@ -917,9 +941,6 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
             cc.c2b = (kTagAttempt << 28) | (uint32_t)((g >> 32) & 0xFFFFu);
         }
         cc.glo = (uint32_t)g;
-        // word of the window position of slot 0 of this lane
-        uint32_t wb = base + off + base_slot;
-        while (wb >= nw) wb -= nw;
         int32_t dj = 0;
 #pragma unroll
         for (int i = 0; i < C; ++i) {
