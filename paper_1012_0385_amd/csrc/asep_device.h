@@ -656,8 +656,11 @@ __device__ uint32_t window_drift(const SimDesc& P, uint32_t sample, uint32_t cma
 // so the output words are exact.
 // Lane lt owns window slots [lt*C, lt*C+C); slot i holds the 64 sites
 // starting at sig + 64*(base + off + i) (mod L).
+// WU: every active lane of a wave serves the same ring (windows, or rings of
+// a whole number of waves), so the ring's sample, shift draws, frame and
+// drift are wave-uniform and live in scalar registers.
 // ---------------------------------------------------------------------------
-template <int C, int MODEL, int V, bool Q0, bool MEAS>
+template <int C, int MODEL, int V, bool Q0, bool MEAS, bool WU>
 __device__ __forceinline__ void sweep_body(const SimDesc& P) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int NPL = (MODEL == kTwoLane) ? 2 : 1;
@@ -683,15 +686,19 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
     const bool act = ring_ok && lt < nact;
     const uint32_t base_slot = lt * C;
     const int cnt = act ? (int)min((uint32_t)C, nslot - base_slot) : 0;
-    const uint32_t sample = P.sample0 + (ring_ok ? ring : 0);
+    uint32_t sample = P.sample0 + (ring_ok ? ring : 0);
+    // lanes past the last ring of a window's workgroup are inactive; they
+    // take the wave's first lane's sample like the rest of the wave
+    if constexpr (WU) sample = __builtin_amdgcn_readfirstlane(sample);
     const uint32_t lane0 = gi * Tr;
     const uint32_t nxt = lane0 + ((lt + 1 < nact) ? lt + 1 : 0);
     // window origin (whole ring: 0) and the output range in window positions
     const uint32_t s0 = sidx * P.seg_n;
     const uint32_t nout = seg ? min(P.seg_n, nw - s0) : nw;
     // left margin: the exact drift of this launch (windows), 0 for whole rings
-    const uint32_t lm =
+    uint32_t lm =
         seg ? window_drift<MODEL, V>(P, P.sample0 + lb / P.segs, (1u << P.sc.lam) - 1u) : 0;
+    if constexpr (WU) lm = __builtin_amdgcn_readfirstlane(lm);  // every lane holds the total
     const uint32_t base = seg ? (s0 + nw - lm) % nw : 0;
     // mask words staged: every position a slot can reach, plus one
     const uint32_t mwords = seg ? nslot + P.halo + 2 : nw;
@@ -902,6 +909,8 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
 
     uint32_t shblk[4] = {0, 0, 0, 0};
     uint64_t shq = ~0ull;
+    uint32_t shv = 0;
+    uint64_t gb = P.g0 - 64;  // g - gb = 64 at the first sub-sweep: fill
     uint32_t ri = 0;
     for (uint64_t g = P.g0;; ++g) {
         if constexpr (MEAS) {
@@ -923,20 +932,37 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
             if (frame != sig) shift_to(frame);
             cc.c2b = (kTagSublattice << 28) | (uint32_t)((g >> 32) & 0xFFFFu);
         } else {
-            const uint64_t quad = g >> 2;
-            if (quad != shq) {
-                const Blk r = philox(0u, (uint32_t)quad,
-                                     (kTagShift << 28) | (uint32_t)((quad >> 32) & 0xFFFFu),
-                                     sample, cc.k0, cc.k1);
-                shblk[0] = r.v[0];
-                shblk[1] = r.v[1];
-                shblk[2] = r.v[2];
-                shblk[3] = r.v[3];
-                shq = quad;
+            uint32_t sw;
+            if constexpr (WU) {
+                // lane l holds the draw of sub-sweep gb + l (its quad's
+                // block, word (gb + l) mod 4): one vector Philox per 64
+                // sub-sweeps, then one lane read each
+                if (g - gb >= 64u) {
+                    gb = g;
+                    const uint64_t gl = g + (threadIdx.x & 63u);
+                    const uint64_t q = gl >> 2;
+                    const Blk r = philox(0u, (uint32_t)q,
+                                         (kTagShift << 28) | (uint32_t)((q >> 32) & 0xFFFFu),
+                                         sample, cc.k0, cc.k1);
+                    const uint32_t wq = (uint32_t)(gl & 3u);
+                    shv = wq == 0 ? r.v[0] : wq == 1 ? r.v[1] : wq == 2 ? r.v[2] : r.v[3];
+                }
+                sw = (uint32_t)__builtin_amdgcn_readlane((int)shv, (int)(g - gb));
+            } else {
+                const uint64_t quad = g >> 2;
+                if (quad != shq) {
+                    const Blk r = philox(0u, (uint32_t)quad,
+                                         (kTagShift << 28) | (uint32_t)((quad >> 32) & 0xFFFFu),
+                                         sample, cc.k0, cc.k1);
+                    shblk[0] = r.v[0];
+                    shblk[1] = r.v[1];
+                    shblk[2] = r.v[2];
+                    shblk[3] = r.v[3];
+                    shq = quad;
+                }
+                const uint32_t gq = (uint32_t)(g & 3u);
+                sw = gq == 0 ? shblk[0] : gq == 1 ? shblk[1] : gq == 2 ? shblk[2] : shblk[3];
             }
-            const uint32_t gq = (uint32_t)(g & 3u);
-            const uint32_t sw =
-                gq == 0 ? shblk[0] : gq == 1 ? shblk[1] : gq == 2 ? shblk[2] : shblk[3];
             shift_to(sw & cmask);
             cc.c2b = (kTagAttempt << 28) | (uint32_t)((g >> 32) & 0xFFFFu);
         }
@@ -1043,9 +1069,9 @@ __device__ __forceinline__ uint32_t find_desc(const SimDesc* __restrict__ d, uin
 }
 
 // One simulation per launch: the descriptor travels in the kernel arguments.
-template <int C, int MODEL, int V, bool Q0, bool MEAS>
+template <int C, int MODEL, int V, bool Q0, bool MEAS, bool WU>
 __global__ __launch_bounds__(sweep_max_block(C, MODEL)) void k_sweep(const SimDesc P) {
-    sweep_body<C, MODEL, V, Q0, MEAS>(P);
+    sweep_body<C, MODEL, V, Q0, MEAS, WU>(P);
 }
 
 // Packed launch: workgroups of several simulations (requests) in one grid,
@@ -1053,7 +1079,7 @@ __global__ __launch_bounds__(sweep_max_block(C, MODEL)) void k_sweep(const SimDe
 template <int C, int MODEL, int V, bool Q0, bool MEAS>
 __global__ __launch_bounds__(sweep_max_block(C, MODEL)) void k_sweep_packed(
     const SimDesc* __restrict__ descs, uint32_t n_desc) {
-    sweep_body<C, MODEL, V, Q0, MEAS>(descs[find_desc(descs, n_desc, blockIdx.x)]);
+    sweep_body<C, MODEL, V, Q0, MEAS, false>(descs[find_desc(descs, n_desc, blockIdx.x)]);
 }
 
 // Dispatch of one model's kernels over (C, variant, q0).  Compiled variants:
@@ -1079,10 +1105,23 @@ inline void launch_one(const SimDesc& one, const SimDesc* descs, uint32_t n_desc
             return;
         }
     }
-    if (meas)
-        hipLaunchKernelGGL((k_sweep<C, MODEL, V, Q, true>), dim3(grid), dim3(block), lds, st, one);
-    else
-        hipLaunchKernelGGL((k_sweep<C, MODEL, V, Q, false>), dim3(grid), dim3(block), lds, st, one);
+    // one ring per wave: windows, or whole rings of whole waves
+    const bool wu = one.segs > 1 || one.lanes_per_ring % 64u == 0;
+    if (meas) {
+        if (wu)
+            hipLaunchKernelGGL((k_sweep<C, MODEL, V, Q, true, true>), dim3(grid), dim3(block),
+                               lds, st, one);
+        else
+            hipLaunchKernelGGL((k_sweep<C, MODEL, V, Q, true, false>), dim3(grid), dim3(block),
+                               lds, st, one);
+    } else {
+        if (wu)
+            hipLaunchKernelGGL((k_sweep<C, MODEL, V, Q, false, true>), dim3(grid), dim3(block),
+                               lds, st, one);
+        else
+            hipLaunchKernelGGL((k_sweep<C, MODEL, V, Q, false, false>), dim3(grid), dim3(block),
+                               lds, st, one);
+    }
 }
 
 template <int MODEL, int C, int V>
