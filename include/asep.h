@@ -251,7 +251,8 @@ typedef struct asep_server_cfg {
     uint64_t hbm_budget_bytes; /* device memory the server may hold for state */
     uint32_t max_queue;        /* pending requests before ASEP_E_BUSY */
     uint32_t max_active;       /* requests resident at once */
-    uint64_t quantum_mcs;      /* MCS a resident request advances per round */
+    uint64_t quantum_mcs;      /* MCS a resident request advances per round
+                                  (0: 1000; at most 2^28, larger values are capped) */
     uint32_t reserved[4];
 } asep_server_cfg;
 

@@ -779,9 +779,17 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
     const int64_t hops0 = (ring_ok && !seg) ? P.hops[ring] : 0;
 
     // Move every slot to the shift sig_new (neighbour exchange through LDS).
+    // Every lane shifts, inactive ones and unused slots included: what they
+    // hold is never read by an active slot (the last active slot takes the
+    // lane nxt's first slot), measured or stored.
+    uint64_t* const xw = xch + (size_t)tid * NPL;
+    uint64_t* const xr = xch + (size_t)nxt * NPL;
     auto shift_to = [&](uint32_t sig_new) {
-        const uint32_t delta = (sig_new - sig) & 63u;
-        const bool wrap = sig_new < sig;
+        const uint32_t delta = (sig_new + 64u - sig) & 63u;
+        // frames are below 64: the start moved back (wrapped) exactly when
+        // sig + delta overshoots sig_new (written so that a wave-uniform frame
+        // keeps both in scalar registers)
+        const bool wrap = sig + delta != sig_new;
         uint64_t na_ = 0, nb_ = 0;
         if (wsync) {
             // the ring lies inside one wave: read the neighbour lane's first
@@ -790,30 +798,22 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
             na_ = shfl_u64(sa[0], src);
             if (MODEL == kTwoLane) nb_ = shfl_u64(sb[0], src);
         } else {
-            uint64_t* xb = xch + (size_t)buf * block * NPL;
-            if (act) {
-                xb[tid * NPL] = sa[0];
-                if (MODEL == kTwoLane) xb[tid * NPL + 1] = sb[0];
-            }
+            const uint32_t bo = buf * block * NPL;
+            xw[bo] = sa[0];
+            if (MODEL == kTwoLane) xw[bo + 1] = sb[0];
             __syncthreads();
-            if (act) {
-                na_ = xb[nxt * NPL];
-                if (MODEL == kTwoLane) nb_ = xb[nxt * NPL + 1];
-            }
+            na_ = xr[bo];
+            if (MODEL == kTwoLane) nb_ = xr[bo + 1];
         }
-        if (act) {
 #pragma unroll
-            for (int i = 0; i < C; ++i) {
-                if (i < cnt) {
-                    uint64_t ha = na_, hb = nb_;
-                    if (i + 1 < C && i + 1 < cnt) {
-                        ha = sa[i + 1 < C ? i + 1 : i];
-                        hb = sb[i + 1 < C ? i + 1 : i];
-                    }
-                    sa[i] = funnel(sa[i], ha, delta);
-                    if (MODEL == kTwoLane) sb[i] = funnel(sb[i], hb, delta);
-                }
+        for (int i = 0; i < C; ++i) {
+            uint64_t ha = na_, hb = nb_;
+            if (i + 1 < C && i + 1 < cnt) {
+                ha = sa[i + 1 < C ? i + 1 : i];
+                hb = sb[i + 1 < C ? i + 1 : i];
             }
+            sa[i] = funnel(sa[i], ha, delta);
+            if (MODEL == kTwoLane) sb[i] = funnel(sb[i], hb, delta);
         }
         if (wrap) {
             off += 1;
@@ -910,17 +910,29 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
     uint32_t shblk[4] = {0, 0, 0, 0};
     uint64_t shq = ~0ull;
     uint32_t shv = 0;
-    uint64_t gb = P.g0 - 64;  // g - gb = 64 at the first sub-sweep: fill
     uint32_t ri = 0;
-    for (uint64_t g = P.g0;; ++g) {
+    // sub-sweeps of this launch (at most 2^30: the host splits longer runs);
+    // the hops of the lane's own cells gather in J32 and fold into J every
+    // 4096 sub-sweeps and before a measurement (a slot takes at most 256
+    // attempts per sub-sweep and a lane at most 16 slots, so |J32| < 2^25)
+    const uint32_t nsub = (uint32_t)(P.g1 - P.g0);
+    int32_t J32 = 0;
+    for (uint32_t t = 0;; ++t) {
+        const uint64_t g = P.g0 + t;
         if constexpr (MEAS) {
             while (ri < P.n_rec && P.rec_g[ri] == g) {
+                J += J32;
+                J32 = 0;
                 shift_to(0);  // uniform call: rings of one workgroup may differ in sig
                 measure(ri);
                 ++ri;
             }
         }
-        if (g >= P.g1) break;
+        if (t >= nsub) break;
+        if ((t & 4095u) == 4095u) {
+            J += J32;
+            J32 = 0;
+        }
         // SCA step: single lane even / odd pairs; two lanes even pairs,
         // A -> B, odd pairs, B -> A.  g is the same for the whole workgroup,
         // so skipping the exchange when the frame stays is a uniform branch.
@@ -934,11 +946,11 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
         } else {
             uint32_t sw;
             if constexpr (WU) {
-                // lane l holds the draw of sub-sweep gb + l (its quad's
-                // block, word (gb + l) mod 4): one vector Philox per 64
+                // lane l holds the draw of sub-sweep g + l from the last
+                // multiple of 64 sub-sweeps into the launch (its quad's
+                // block, word (g + l) mod 4): one vector Philox per 64
                 // sub-sweeps, then one lane read each
-                if (g - gb >= 64u) {
-                    gb = g;
+                if ((t & 63u) == 0) {
                     const uint64_t gl = g + (threadIdx.x & 63u);
                     const uint64_t q = gl >> 2;
                     const Blk r = philox(0u, (uint32_t)q,
@@ -947,7 +959,7 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
                     const uint32_t wq = (uint32_t)(gl & 3u);
                     shv = wq == 0 ? r.v[0] : wq == 1 ? r.v[1] : wq == 2 ? r.v[2] : r.v[3];
                 }
-                sw = (uint32_t)__builtin_amdgcn_readlane((int)shv, (int)(g - gb));
+                sw = (uint32_t)__builtin_amdgcn_readlane((int)shv, (int)(t & 63u));
             } else {
                 const uint64_t quad = g >> 2;
                 if (quad != shq) {
@@ -1025,8 +1037,9 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
                 if (!seg || pos - lm < nout) dj += d;
             }
         }
-        J += dj;
+        J32 += dj;
     }
+    J += J32;
     shift_to(0);
 #pragma unroll
     for (int i = 0; i < C; ++i) {

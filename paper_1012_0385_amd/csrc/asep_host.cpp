@@ -608,18 +608,36 @@ static int sweep_launch(asep_sim* s, const SimDesc& d) {
 // Queue the work from the current time to t_end (MCS), measuring at
 // times[0..n) (ascending, within [t, t_end], n <= rec_cap) into the device
 // staging; the records are copied to host_out (n x samples) asynchronously.
+// Sub-sweeps of one whole-ring launch at most (the kernel counts them in 32 bits).
+static const uint64_t kMaxLaunchSub = 1ull << 30;
+
 static int enqueue_to(asep_sim* s, uint64_t t_end, const uint64_t* times, uint32_t n,
                       Record* host_out) {
     const Resolved& r = s->r;
     const uint32_t S = r.sc.S;
     SimDesc d = make_desc(s);
     if (!s->plan.seg) {
-        for (uint32_t i = 0; i < n; ++i) d.rec_g[i] = times[i] * S;
-        d.g0 = s->t * S;
-        d.g1 = t_end * S;
-        d.n_rec = n;
-        int rc = sweep_launch(s, d);
-        if (rc) return rc;
+        // whole rings: one launch per at most kMaxLaunchSub sub-sweeps, each
+        // with the measurements in [g0, g1) (the last one also at g1)
+        uint64_t g = s->t * S;
+        const uint64_t g_end = t_end * S;
+        uint32_t ri = 0;
+        do {
+            const uint64_t gl = std::min<uint64_t>(g_end, g + kMaxLaunchSub);
+            uint32_t nr = 0;
+            while (ri + nr < n && (times[ri + nr] * S < gl || (gl == g_end && times[ri + nr] * S == gl))) {
+                d.rec_g[nr] = times[ri + nr] * S;
+                ++nr;
+            }
+            d.g0 = g;
+            d.g1 = gl;
+            d.n_rec = nr;
+            d.rec = s->rec + (size_t)ri * r.P.samples;
+            int rc = sweep_launch(s, d);
+            if (rc) return rc;
+            ri += nr;
+            g = gl;
+        } while (g < g_end);
     } else {
         // windows: launches of at most K sub-sweeps between the two buffers,
         // measurements from the words of whole rings between launches
@@ -806,6 +824,7 @@ int sim_pack_prepare(asep_sim* s, uint64_t t_end, const uint64_t* times, uint32_
                      SimDesc* d) {
     if (s->plan.seg || n > s->rec_cap || t_end < s->t) return ASEP_E_INVAL;
     const uint32_t S = s->r.sc.S;
+    if ((t_end - s->t) * S > kMaxLaunchSub) return ASEP_E_INVAL;  // one launch
     *d = make_desc(s);
     for (uint32_t i = 0; i < n; ++i) d->rec_g[i] = times[i] * S;
     d->g0 = s->t * S;

@@ -295,6 +295,8 @@ int server_create_with(const asep_server_cfg* cfg, std::unique_ptr<Executor> x,
     if (!S->cfg.max_queue) S->cfg.max_queue = 1024;
     if (!S->cfg.max_active) S->cfg.max_active = 64;
     if (!S->cfg.quantum_mcs) S->cfg.quantum_mcs = 1000;
+    // a quantum is one launch of at most 2^30 sub-sweeps (4 per MCS at most)
+    if (S->cfg.quantum_mcs > (1ull << 28)) S->cfg.quantum_mcs = 1ull << 28;
     if (!S->cfg.hbm_budget_bytes) S->cfg.hbm_budget_bytes = (uint64_t)8 << 30;
     S->X = std::move(x);
     try {
