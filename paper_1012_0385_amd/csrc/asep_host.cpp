@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -609,7 +610,19 @@ static int sweep_launch(asep_sim* s, const SimDesc& d) {
 // times[0..n) (ascending, within [t, t_end], n <= rec_cap) into the device
 // staging; the records are copied to host_out (n x samples) asynchronously.
 // Sub-sweeps of one whole-ring launch at most (the kernel counts them in 32 bits).
+// ASEP_MAX_LAUNCH_SUBSWEEPS (1 .. 2^30) lowers it, so that tests can run the
+// split of long runs at small sizes.
 static const uint64_t kMaxLaunchSub = 1ull << 30;
+
+static uint64_t max_launch_sub() {
+    const char* e = std::getenv("ASEP_MAX_LAUNCH_SUBSWEEPS");
+    if (e && *e) {
+        char* end = nullptr;
+        const unsigned long long v = std::strtoull(e, &end, 10);
+        if (end && *end == '\0' && v >= 1 && v <= kMaxLaunchSub) return v;
+    }
+    return kMaxLaunchSub;
+}
 
 static int enqueue_to(asep_sim* s, uint64_t t_end, const uint64_t* times, uint32_t n,
                       Record* host_out) {
@@ -621,9 +634,10 @@ static int enqueue_to(asep_sim* s, uint64_t t_end, const uint64_t* times, uint32
         // with the measurements in [g0, g1) (the last one also at g1)
         uint64_t g = s->t * S;
         const uint64_t g_end = t_end * S;
+        const uint64_t cap = max_launch_sub();
         uint32_t ri = 0;
         do {
-            const uint64_t gl = std::min<uint64_t>(g_end, g + kMaxLaunchSub);
+            const uint64_t gl = std::min<uint64_t>(g_end, g + cap);
             uint32_t nr = 0;
             while (ri + nr < n && (times[ri + nr] * S < gl || (gl == g_end && times[ri + nr] * S == gl))) {
                 d.rec_g[nr] = times[ri + nr] * S;

@@ -306,3 +306,24 @@ def test_launch_shape_invariance(base):
             assert np.array_equal(x.J, y.J) and np.array_equal(x.N, y.N), shape
         for a, b in zip(states, ref_states):
             assert np.array_equal(a, b), shape
+
+
+@pytest.mark.parametrize("base", [
+    dict(L=8192, p=1.0, q=0.0, init=1, seed=6, stream=1),
+    dict(L=1024, p=0.5, q=0.5, init=1, seed=6, stream=2),
+    dict(L=4096, init=1, p=0.75, q=0.25, slow_frac=0.5, slow_factor=0.5, seed=6, stream=3),
+    dict(L=4096, model=1, init=1, density=0.3, p=1.0, q=1.0, lane_rate=0.1, turn_frac=0.05,
+         seed=6, stream=4),
+])
+def test_whole_ring_launch_split(base, monkeypatch):
+    # a whole-ring run cut into launches of at most 37 sub-sweeps (measurement
+    # times inside, at and between the cuts) is the same run, word for word
+    times = [0, 3, 9, 10, 31, 40]
+    ref, ref_states = _records_and_states(dict(base, windows=1), times, 5)
+    monkeypatch.setenv("ASEP_MAX_LAUNCH_SUBSWEEPS", "37")
+    got, states = _records_and_states(dict(base, windows=1), times, 5)
+    for x, y in zip(got, ref):
+        assert np.array_equal(x.S1, y.S1) and x.S2 == y.S2
+        assert np.array_equal(x.J, y.J) and np.array_equal(x.N, y.N)
+    for a, b in zip(states, ref_states):
+        assert np.array_equal(a, b)
