@@ -917,6 +917,8 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
     // attempts per sub-sweep and a lane at most 16 slots, so |J32| < 2^25)
     const uint32_t nsub = (uint32_t)(P.g1 - P.g0);
     int32_t J32 = 0;
+    // first slot of this lane's wave (windows: one ring per workgroup, lt = tid)
+    const uint32_t wave_slot0 = __builtin_amdgcn_readfirstlane(lt & ~63u) * (uint32_t)C;
     for (uint32_t t = 0;; ++t) {
         const uint64_t g = P.g0 + t;
         if constexpr (MEAS) {
@@ -980,9 +982,14 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
         }
         cc.glo = (uint32_t)g;
         int32_t dj = 0;
+        // Windows: content moves at most one slot to the left per frame
+        // change, and nsub - t of them follow this sub-sweep, so slots at or
+        // past nout + nsub - t can no longer reach the output (nor are they
+        // owned).  A wave whose first slot is there skips its attempts.
+        const bool live = !seg || t + wave_slot0 < nout + nsub;
 #pragma unroll
         for (int i = 0; i < C; ++i) {
-            if (i < cnt) {
+            if (live && i < cnt) {
                 uint32_t w = wb + (uint32_t)i;
                 if (w >= nw) w -= nw;
                 const uint32_t pos = off + base_slot + (uint32_t)i;  // window position
