@@ -50,9 +50,9 @@ UPDATE_SLOTS = 10
 # only for the kernel sources they were taken on (SHA-256 prefix below) and
 # for that launch shape; otherwise the bench reports traffic as unknown.
 SWEEP_TRAFFIC = {
-    "src_sha256": "d4e0a996104af012",
+    "src_sha256": "35b389de9b2f9dd3",
     "launch_shape": {"windows": 4, "window_sweeps": 255, "rings_per_wg": 0},
-    "fetch_kib": 836.25,   # KPZ 834.2, EW 838.3
+    "fetch_kib": 841.25,   # KPZ 839.7, EW 842.8
     "write_kib": 1032.0,
     "fetch_scale": 2.0,    # 4 GiB copy: FETCH_SIZE 2097206 KiB
     "write_scale": 1.0,    # 4 GiB copy: WRITE_SIZE 4194304 KiB
