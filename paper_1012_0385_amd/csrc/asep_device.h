@@ -155,6 +155,11 @@ struct CellCtx {
     // compared bits (o >> 2) mod 2^b hops (the pattern repeats every 2^(2+b)
     // bits, so any higher bits of the offset select the same outcome).
     uint32_t lutP;
+    // Columnar disorder, when the offset fits five bits: bit o says whether
+    // pair o mod 4, compared bits (o >> 2) mod 2^b, the forward mark at bit
+    // 2+b and (with backward hops) the backward mark at bit 3+b hop;
+    // repeated likewise above the bits in use.
+    uint32_t lutD;
 };
 
 // Generic single-lane cell: any cell size ell <= 64 located at bit `bb` of
@@ -225,7 +230,31 @@ __device__ __forceinline__ int32_t cell_ring_fast(uint64_t& x, uint64_t m0, uint
                 const int64_t sx = (int64_t)x >> j;
                 const uint32_t pr = (uint32_t)sx & 3u;
                 uint32_t f;
-                if (BB >= 0 && BB <= 2 && !DIS) {
+                constexpr bool DTAB = DIS && BB >= 0 && 3 + BB + (Q0 ? 0 : 1) <= 5;
+                if (DTAB) {
+                    // pair, compared bits and the marks of the bond index
+                    // one outcome bit (lutD); then as below
+                    uint32_t hi = (uint32_t)(m0 >> j);  // bit 0: forward mark at j
+                    if (!Q0)  // bit 1: backward mark at j+1
+                        hi = __builtin_amdgcn_bitop3_b32(hi, (uint32_t)(m1 >> j), 1u, 0xE4);
+                    uint32_t off;
+                    if (BB > 0) {
+                        const uint32_t rs = sh >= 2 ? u >> (sh - 2) : u << (2 - sh);
+                        off = __builtin_amdgcn_bitop3_b32(insert_low2((uint32_t)sx, rs),
+                                                          hi << (2 + BB), (1u << (2 + BB)) - 1u,
+                                                          0xE4);
+                    } else {
+                        off = insert_low2((uint32_t)sx, hi << 2);
+                    }
+                    const uint32_t F = (uint32_t)__builtin_amdgcn_sbfe((int32_t)c.lutD, off, 1);
+                    const uint64_t M = 3ull << j;
+                    const uint32_t lo = xor_masked((uint32_t)x, (uint32_t)M, F);
+                    const uint32_t hw = xor_masked((uint32_t)(x >> 32), (uint32_t)(M >> 32), F);
+                    x = ((uint64_t)hw << 32) | lo;
+                    dj += (int32_t)F;
+                    if (!Q0) dj += (int32_t)(F & ~(uint32_t)sx & 2u);
+                    continue;
+                } else if (BB >= 0 && BB <= 2 && !DIS) {
                     // Offset into lutP: the pair in bits 0-1, the compared
                     // bits above it (v_bfe takes the offset mod 32, so the
                     // sites beyond the pair only repeat the pattern).  F is
@@ -269,7 +298,7 @@ __device__ __forceinline__ int32_t cell_ring_fast(uint64_t& x, uint64_t m0, uint
             }
         }
     }
-    if (BB >= 0 && BB <= 2 && !DIS) return Q0 ? -dj : dj;
+    if (BB >= 0 && BB <= 2 && (!DIS || 3 + BB + (Q0 ? 0 : 1) <= 5)) return Q0 ? -dj : dj;
     return Q0 ? dj / 3 : dj;
 }
 
@@ -733,11 +762,17 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
     cc.T3 = P.sc.T[3];
     cc.lut = (P.sc.T[0] << 8) | (P.sc.T[1] << 16);
     cc.lutP = 0;
+    cc.lutD = 0;
     if (P.sc.b <= 2) {
+        const uint32_t b = P.sc.b;
         for (uint32_t o = 0; o < 32; ++o) {
-            const uint32_t pr = o & 3u, rv = (o >> 2) & ((1u << P.sc.b) - 1u);
+            const uint32_t pr = o & 3u, rv = (o >> 2) & ((1u << b) - 1u);
             const bool hop = (pr == 1u && rv < P.sc.T[0]) || (pr == 2u && rv < P.sc.T[1]);
             cc.lutP |= (hop ? 1u : 0u) << o;
+            const uint32_t mp = (o >> (2 + b)) & 1u, mq = Q0 ? 0u : (o >> (3 + b)) & 1u;
+            const bool hopd = (pr == 1u && rv < (mp ? P.sc.T[2] : P.sc.T[0])) ||
+                              (pr == 2u && rv < (mq ? P.sc.T[3] : P.sc.T[1]));
+            cc.lutD |= (hopd ? 1u : 0u) << o;
         }
     }
 

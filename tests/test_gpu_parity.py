@@ -102,6 +102,21 @@ def test_disorder(orc):
     compare(orc, kw, [0, 9, 20], 5)
 
 
+@pytest.mark.parametrize("rates", [
+    dict(p=1.0, q=1.0, slow_factor=0.5),    # 1 compared bit, marks of both directions
+    dict(p=1.0, q=0.0, slow_factor=0.25),   # 2 compared bits, forward marks only
+    dict(p=0.5, q=0.0, slow_factor=0.5),    # 2 compared bits
+    dict(p=1.0, q=1.0, slow_factor=0.0),    # 0 compared bits: slow bonds closed
+    dict(p=0.5, q=0.5, slow_factor=1.0),    # marks present, rates equal
+])
+def test_disorder_outcome_bits(orc, rates):
+    # rates on a grid of 1/2 or 1/4: the attempt reads its outcome from one
+    # bit indexed by the pair, the compared bits and the marks
+    kw = dict(L=4096, slow_frac=0.3, samples_per_disorder=2, seed=8, stream=5, **rates)
+    compare(orc, kw, [0, 5, 21], 5)
+    compare(orc, dict(kw, windows=3, window_sweeps=7), [0, 5, 21], 5)
+
+
 def test_disorder_masks_match_oracle(orc):
     kw = dict(L=4096, p=0.75, q=0.5, slow_frac=0.1, slow_factor=0.5, samples_per_disorder=4,
               seed=3, stream=2, sample_offset=6)
