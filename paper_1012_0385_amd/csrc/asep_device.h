@@ -150,7 +150,6 @@ struct CellCtx {
     uint32_t k0, k1;  // key
     uint32_t na, nblk, b, w, A;
     uint32_t T0, T1, T2, T3;
-    uint32_t lut;     // packed 8-bit thresholds {0, T0, T1, 0} for pair 0..3
     // With at most 2 compared bits: bit o says whether pair o mod 4 with
     // compared bits (o >> 2) mod 2^b hops (the pattern repeats every 2^(2+b)
     // bits, so any higher bits of the offset select the same outcome).
@@ -283,8 +282,6 @@ __device__ __forceinline__ int32_t cell_ring_fast(uint64_t& x, uint64_t m0, uint
                         uint32_t tq = 0;
                         if (!Q0) tq = (((m1 >> j) >> 1) & 1u) ? c.T3 : c.T1;
                         tsel = pr == 1u ? tp : (pr == 2u ? tq : 0u);
-                    } else if (BB >= 0 && BB <= 7) {
-                        tsel = bfe(c.lut, (uint32_t)sx << 3, 8);
                     } else {
                         tsel = pr == 1u ? c.T0 : (pr == 2u ? c.T1 : 0u);
                     }
@@ -760,7 +757,6 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
     cc.T1 = P.sc.T[1];
     cc.T2 = P.sc.T[2];
     cc.T3 = P.sc.T[3];
-    cc.lut = (P.sc.T[0] << 8) | (P.sc.T[1] << 16);
     cc.lutP = 0;
     cc.lutD = 0;
     if (P.sc.b <= 2) {
