@@ -15,8 +15,9 @@ the batched form.
 
 The JSON line also carries the ALU roofline of the dominant kernel (the
 sweep kernel: per-launch algorithmic instruction slots over its average
-duration from HIP events on its own stream, taken in the plain form so that
-no two launches overlap) and the CPU oracle timed on
+duration from HIP events that the kernel's dispatch itself records on the
+sweep's stream (`hipExtLaunchKernel`), taken in the plain form so that no
+two launches overlap) and the CPU oracle timed on
 the host cores over a bounded prefix of the same workload.
 """
 import argparse

@@ -11,6 +11,7 @@
 //   two-sub-lattice update: (slot w, lo32(g), 8<<28 | blk<<16 | hi16(g), sample)
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -1143,7 +1144,8 @@ __global__ __launch_bounds__(sweep_max_block(C, MODEL)) void k_sweep_packed(
 // simulations does (`one` then carries n_rec > 0).
 template <int MODEL, int C, int V, bool Q>
 inline void launch_one(const SimDesc& one, const SimDesc* descs, uint32_t n_desc, uint32_t grid,
-                       uint32_t block, size_t lds, hipStream_t st) {
+                       uint32_t block, size_t lds, hipStream_t st, hipEvent_t ev0,
+                       hipEvent_t ev1) {
     const bool meas = one.n_rec > 0;
     if constexpr (C <= 4) {
         if (descs) {
@@ -1156,68 +1158,70 @@ inline void launch_one(const SimDesc& one, const SimDesc* descs, uint32_t n_desc
             return;
         }
     }
-    // one ring per wave: windows, or whole rings of whole waves
+    // one ring per wave: windows, or whole rings of whole waves; the
+    // dispatch records the kernel's own start and end in ev0 / ev1 if given
     const bool wu = one.segs > 1 || one.lanes_per_ring % 64u == 0;
     if (meas) {
         if (wu)
-            hipLaunchKernelGGL((k_sweep<C, MODEL, V, Q, true, true>), dim3(grid), dim3(block),
-                               lds, st, one);
+            hipExtLaunchKernelGGL((k_sweep<C, MODEL, V, Q, true, true>), dim3(grid), dim3(block),
+                                  (uint32_t)lds, st, ev0, ev1, 0u, one);
         else
-            hipLaunchKernelGGL((k_sweep<C, MODEL, V, Q, true, false>), dim3(grid), dim3(block),
-                               lds, st, one);
+            hipExtLaunchKernelGGL((k_sweep<C, MODEL, V, Q, true, false>), dim3(grid), dim3(block),
+                                  (uint32_t)lds, st, ev0, ev1, 0u, one);
     } else {
         if (wu)
-            hipLaunchKernelGGL((k_sweep<C, MODEL, V, Q, false, true>), dim3(grid), dim3(block),
-                               lds, st, one);
+            hipExtLaunchKernelGGL((k_sweep<C, MODEL, V, Q, false, true>), dim3(grid), dim3(block),
+                                  (uint32_t)lds, st, ev0, ev1, 0u, one);
         else
-            hipLaunchKernelGGL((k_sweep<C, MODEL, V, Q, false, false>), dim3(grid), dim3(block),
-                               lds, st, one);
+            hipExtLaunchKernelGGL((k_sweep<C, MODEL, V, Q, false, false>), dim3(grid),
+                                  dim3(block), (uint32_t)lds, st, ev0, ev1, 0u, one);
     }
 }
 
 template <int MODEL, int C, int V>
 inline void launch_q(const SweepKernel& k, const SimDesc& one, const SimDesc* descs,
-                     uint32_t n_desc, uint32_t grid, uint32_t block, size_t lds, hipStream_t st) {
+                     uint32_t n_desc, uint32_t grid, uint32_t block, size_t lds, hipStream_t st,
+                     hipEvent_t ev0, hipEvent_t ev1) {
     if constexpr (MODEL == kTwoLane) {
-        launch_one<MODEL, C, V, false>(one, descs, n_desc, grid, block, lds, st);
+        launch_one<MODEL, C, V, false>(one, descs, n_desc, grid, block, lds, st, ev0, ev1);
     } else {
         if (k.q0)
-            launch_one<MODEL, C, V, true>(one, descs, n_desc, grid, block, lds, st);
+            launch_one<MODEL, C, V, true>(one, descs, n_desc, grid, block, lds, st, ev0, ev1);
         else
-            launch_one<MODEL, C, V, false>(one, descs, n_desc, grid, block, lds, st);
+            launch_one<MODEL, C, V, false>(one, descs, n_desc, grid, block, lds, st, ev0, ev1);
     }
 }
 
 template <int MODEL, int C>
 inline hipError_t launch_c(const SweepKernel& k, const SimDesc& one, const SimDesc* descs,
                            uint32_t n_desc, uint32_t grid, uint32_t block, size_t lds,
-                           hipStream_t st) {
+                           hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
     if (descs && C > 4) return hipErrorInvalidValue;
     if (k.variant == kSca) {
         // two lanes hold twice the state: 16 slots per lane would spill
         if constexpr (MODEL != kTwoLane || C <= 8) {
-            launch_q<MODEL, C, kSca>(k, one, descs, n_desc, grid, block, lds, st);
+            launch_q<MODEL, C, kSca>(k, one, descs, n_desc, grid, block, lds, st, ev0, ev1);
             return hipSuccess;
         }
         return hipErrorInvalidValue;
     }
     if (k.variant == kGeneric) {
-        launch_one<MODEL, C, kGeneric, false>(one, descs, n_desc, grid, block, lds, st);
+        launch_one<MODEL, C, kGeneric, false>(one, descs, n_desc, grid, block, lds, st, ev0, ev1);
         return hipSuccess;
     }
     if constexpr (C <= 8) {
         if constexpr (MODEL == kTwoLane) {
             switch (k.variant) {
-                case kF4B0: launch_one<MODEL, C, kF4B0, false>(one, descs, n_desc, grid, block, lds, st); return hipSuccess;
-                case kF1: launch_one<MODEL, C, kF1, false>(one, descs, n_desc, grid, block, lds, st); return hipSuccess;
+                case kF4B0: launch_one<MODEL, C, kF4B0, false>(one, descs, n_desc, grid, block, lds, st, ev0, ev1); return hipSuccess;
+                case kF1: launch_one<MODEL, C, kF1, false>(one, descs, n_desc, grid, block, lds, st, ev0, ev1); return hipSuccess;
                 default: return hipErrorInvalidValue;
             }
         } else {
             switch (k.variant) {
-                case kF5B0: launch_q<MODEL, C, kF5B0>(k, one, descs, n_desc, grid, block, lds, st); return hipSuccess;
-                case kF4B1: launch_q<MODEL, C, kF4B1>(k, one, descs, n_desc, grid, block, lds, st); return hipSuccess;
-                case kF4B2: launch_q<MODEL, C, kF4B2>(k, one, descs, n_desc, grid, block, lds, st); return hipSuccess;
-                case kF1: launch_q<MODEL, C, kF1>(k, one, descs, n_desc, grid, block, lds, st); return hipSuccess;
+                case kF5B0: launch_q<MODEL, C, kF5B0>(k, one, descs, n_desc, grid, block, lds, st, ev0, ev1); return hipSuccess;
+                case kF4B1: launch_q<MODEL, C, kF4B1>(k, one, descs, n_desc, grid, block, lds, st, ev0, ev1); return hipSuccess;
+                case kF4B2: launch_q<MODEL, C, kF4B2>(k, one, descs, n_desc, grid, block, lds, st, ev0, ev1); return hipSuccess;
+                case kF1: launch_q<MODEL, C, kF1>(k, one, descs, n_desc, grid, block, lds, st, ev0, ev1); return hipSuccess;
                 default: return hipErrorInvalidValue;
             }
         }
@@ -1228,15 +1232,15 @@ inline hipError_t launch_c(const SweepKernel& k, const SimDesc& one, const SimDe
 template <int MODEL>
 inline hipError_t launch_model(const SweepKernel& k, const SimDesc& one, const SimDesc* descs,
                                uint32_t n_desc, uint32_t grid, uint32_t block, size_t lds,
-                               hipStream_t st) {
+                               hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
     (void)hipGetLastError();  // drop errors left by earlier, unrelated calls
     hipError_t e;
     switch (k.C) {
-        case 1: e = launch_c<MODEL, 1>(k, one, descs, n_desc, grid, block, lds, st); break;
-        case 2: e = launch_c<MODEL, 2>(k, one, descs, n_desc, grid, block, lds, st); break;
-        case 4: e = launch_c<MODEL, 4>(k, one, descs, n_desc, grid, block, lds, st); break;
-        case 8: e = launch_c<MODEL, 8>(k, one, descs, n_desc, grid, block, lds, st); break;
-        case 16: e = launch_c<MODEL, 16>(k, one, descs, n_desc, grid, block, lds, st); break;
+        case 1: e = launch_c<MODEL, 1>(k, one, descs, n_desc, grid, block, lds, st, ev0, ev1); break;
+        case 2: e = launch_c<MODEL, 2>(k, one, descs, n_desc, grid, block, lds, st, ev0, ev1); break;
+        case 4: e = launch_c<MODEL, 4>(k, one, descs, n_desc, grid, block, lds, st, ev0, ev1); break;
+        case 8: e = launch_c<MODEL, 8>(k, one, descs, n_desc, grid, block, lds, st, ev0, ev1); break;
+        case 16: e = launch_c<MODEL, 16>(k, one, descs, n_desc, grid, block, lds, st, ev0, ev1); break;
         default: e = hipErrorInvalidValue;
     }
     if (e != hipSuccess) return e;

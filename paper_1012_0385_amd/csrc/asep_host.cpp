@@ -592,11 +592,12 @@ static int sweep_launch(asep_sim* s, const SimDesc& d) {
             if (rc) return rc;
         }
         slot = s->ev_head;
-        HIP_OR_FAIL(hipEventRecord(s->ev[2 * slot], s->stream));
     }
-    HIP_OR_FAIL(launch_sweep(pl.kern, d, nullptr, 0, pl.grid, pl.block, pl.lds, s->stream));
+    // timing: the dispatch records the kernel's own start and end
+    HIP_OR_FAIL(launch_sweep(pl.kern, d, nullptr, 0, pl.grid, pl.block, pl.lds, s->stream,
+                             prof ? s->ev[2 * slot] : nullptr,
+                             prof ? s->ev[2 * slot + 1] : nullptr));
     if (prof) {
-        HIP_OR_FAIL(hipEventRecord(s->ev[2 * slot + 1], s->stream));
         const Resolved& r = s->r;
         s->ev_att[slot] = (d.g1 - d.g0) * (uint64_t)r.P.samples * r.P.L * (r.planes == 2 ? 4 : 1) /
                           r.sc.S;

@@ -78,23 +78,25 @@ hipError_t launch_rough(const uint64_t* words, const int64_t* hops, Record* rec,
                         uint32_t planes, uint32_t nw, hipStream_t st);
 
 // Sweep launch: `one` describes the whole launch when descs == nullptr;
-// otherwise descs[0..n_desc) (device memory, sorted by wg_begin) do.
+// otherwise descs[0..n_desc) (device memory, sorted by wg_begin) do.  With
+// ev0 and ev1 (single-simulation launches only) the dispatch itself records
+// the kernel's start and end in them.
 struct SweepKernel {
     uint32_t C, model, variant;
     bool q0;
 };
 hipError_t launch_sweep(const SweepKernel& k, const SimDesc& one, const SimDesc* descs,
                         uint32_t n_desc, uint32_t grid, uint32_t block, size_t lds,
-                        hipStream_t st);
+                        hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 hipError_t launch_sweep_plain(const SweepKernel& k, const SimDesc& one, const SimDesc* descs,
                               uint32_t n_desc, uint32_t grid, uint32_t block, size_t lds,
-                              hipStream_t st);
+                              hipStream_t st, hipEvent_t ev0, hipEvent_t ev1);
 hipError_t launch_sweep_disorder(const SweepKernel& k, const SimDesc& one, const SimDesc* descs,
                                  uint32_t n_desc, uint32_t grid, uint32_t block, size_t lds,
-                                 hipStream_t st);
+                                 hipStream_t st, hipEvent_t ev0, hipEvent_t ev1);
 hipError_t launch_sweep_two_lane(const SweepKernel& k, const SimDesc& one, const SimDesc* descs,
                                  uint32_t n_desc, uint32_t grid, uint32_t block, size_t lds,
-                                 hipStream_t st);
+                                 hipStream_t st, hipEvent_t ev0, hipEvent_t ev1);
 uint32_t sweep_block_limit(uint32_t C, uint32_t model);
 size_t sweep_lds_bytes(uint32_t block, uint32_t planes, uint32_t rings_per_wg, uint32_t mplanes,
                        uint32_t mwords);

@@ -202,11 +202,14 @@ bool sweep_variant_compiled(uint32_t C, uint32_t model, uint32_t variant) {
 
 hipError_t launch_sweep(const SweepKernel& k, const SimDesc& one, const SimDesc* descs,
                         uint32_t n_desc, uint32_t grid, uint32_t block, size_t lds,
-                        hipStream_t st) {
+                        hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
     switch (k.model) {
-        case kPlain: return launch_sweep_plain(k, one, descs, n_desc, grid, block, lds, st);
-        case kDisorder: return launch_sweep_disorder(k, one, descs, n_desc, grid, block, lds, st);
-        case kTwoLane: return launch_sweep_two_lane(k, one, descs, n_desc, grid, block, lds, st);
+        case kPlain:
+            return launch_sweep_plain(k, one, descs, n_desc, grid, block, lds, st, ev0, ev1);
+        case kDisorder:
+            return launch_sweep_disorder(k, one, descs, n_desc, grid, block, lds, st, ev0, ev1);
+        case kTwoLane:
+            return launch_sweep_two_lane(k, one, descs, n_desc, grid, block, lds, st, ev0, ev1);
         default: return hipErrorInvalidValue;
     }
 }
