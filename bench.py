@@ -51,7 +51,7 @@ UPDATE_SLOTS = 10
 # only for the kernel sources they were taken on (SHA-256 prefix below) and
 # for that launch shape; otherwise the bench reports traffic as unknown.
 SWEEP_TRAFFIC = {
-    "src_sha256": "0c9388f9245bb254",
+    "src_sha256": "04c688485efbd76c",
     "launch_shape": {"windows": 4, "window_sweeps": 255, "rings_per_wg": 0},
     "fetch_kib": 841.25,   # KPZ 839.7, EW 842.8
     "write_kib": 1032.0,
