@@ -454,3 +454,41 @@ def test_schedule_matches_random_sequential(orc):
     dd, rs = np.array(dd), np.array(rs)
     z = (dd.mean(0) - rs.mean(0)) / np.sqrt(dd.var(0) / n + rs.var(0) / n)
     assert np.all(np.abs(z) < 4)
+
+
+# --------------------------------------------------------------------------- hop count
+def _hop_cases(orc):
+    two = dict(model=orc.TWO_LANE, lane_rate=0.3, turn_frac=0.2)
+    return [
+        ("plain", orc.Params(L=512, p=0.8, q=0.3)),
+        ("plain-ell4", orc.Params(L=256, p=0.6, q=0.4, cell_log2=2, subsweeps=1)),
+        ("disorder", orc.Params(L=1024, p=0.75, q=0.25, slow_frac=0.3, slow_factor=0.5, rbits=26)),
+        ("two-lane", orc.Params(L=512, p=0.9, q=0.7, **two)),
+        ("sublattice", orc.Params(L=512, p=0.7, q=0.2, schedule=orc.SCHED_SUBLATTICE)),
+        ("two-lane sublattice", orc.Params(L=512, model=orc.TWO_LANE, p=0.5, q=0.5,
+                                           lane_rate=0.8, slow_frac=0.5, slow_factor=0.25,
+                                           schedule=orc.SCHED_SUBLATTICE)),
+    ]
+
+
+@pytest.mark.parametrize("case", range(6))
+def test_hops_equal_position_sum_change(orc, case):
+    """The hop count J (+1 per hop to the right, -1 per hop to the left; on two
+    lanes lane A hops right and lane B left, lane changes count nothing) moves
+    the particles' position sum P = sum_y y n_y by J modulo L: a hop within the
+    ring changes P by +-1, one across the closing bond by -+(L-1), and a lane
+    change keeps it.  The identity ties J to the state alone, so a hop counted
+    with the wrong sign, twice, or not at all shows up."""
+    name, P = _hop_cases(orc)[case]
+    P.init = orc.INIT_BERNOULLI
+    P.density = 0.4
+    L = P.L
+    for sample in (0, 3):
+        st0 = orc.init_state(P, sample).astype(np.int64)
+        r = orc.run(P, sample, [0, 4, 11])
+        st1 = r.state.astype(np.int64)
+        pos = np.tile(np.arange(L, dtype=np.int64), len(st0) // L)
+        dP = int((pos * (st1 - st0)).sum())
+        J = int(r.J[-1])
+        assert J != 0, name
+        assert (J - dP) % L == 0, (name, sample, J, dP)
