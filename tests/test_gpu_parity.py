@@ -281,6 +281,51 @@ def test_run_batch_equals_alone(orc):
         s.close()
 
 
+def _site_bits(words):
+    return np.unpackbits(np.asarray(words, dtype="<u8").view(np.uint8), bitorder="little")
+
+
+def test_benchmark_configuration(orc):
+    # the benchmark exactly: 64 KPZ and 64 EW rings of 2^17 sites from the flat
+    # start, at the tuned launch shape, both ensembles advanced together; sampled
+    # rings against the oracle, every ring against the conservation law and the
+    # hop-count identity (J = change of the position sum modulo L)
+    from concurrent.futures import ThreadPoolExecutor
+
+    from paper_1012_0385_amd import tune
+
+    L, R, times = 1 << 17, 64, [0, 1, 8, 64, 200]
+    kws = [dict(L=L, p=1.0, q=0.0, seed=1, stream=0), dict(L=L, p=0.5, q=0.5, seed=1, stream=1)]
+    sims = []
+    for kw in kws:
+        shape = tune.lookup(kw, R)
+        print("case: benchmark ensemble", kw, shape, flush=True)
+        sims.append(A.Simulation(A.make_params(samples=R, **kw, **shape), stream=torch.cuda.Stream()))
+    got = A.run_batch(sims, times)
+    pos = np.arange(L, dtype=np.int64)
+    P0 = int(pos[::2].sum())
+    picks = (0, 37, R - 1)
+    with ThreadPoolExecutor(6) as ex:
+        refs = {(m, i): ex.submit(orc.run, oracle_params(orc, kw), i, times)
+                for m, kw in enumerate(kws) for i in picks}
+        for m, (kw, sim, g) in enumerate(zip(kws, sims, got)):
+            for i in range(R):
+                bits = _site_bits(sim.read_state(i))
+                assert int(bits.sum()) == L // 2 and all(int(r.N[i]) == L // 2 for r in g), (m, i)
+                dP = int((pos * bits).sum()) - P0
+                assert (int(g[-1].J[i]) - dP) % L == 0, (m, i)
+            for i in picks:
+                ref = refs[(m, i)].result()
+                for ti in range(len(times)):
+                    assert g[ti].S1[i] == ref.S1[ti] and g[ti].S2[i] == ref.S2[ti], (m, i, times[ti])
+                    assert g[ti].J[i] == ref.J[ti], (m, i, times[ti])
+                    w = orc.w2(L, int(ref.S1[ti]), ref.S2[ti])
+                    assert abs(g[ti].w2[i] - w) <= 1e-12 * max(abs(w), 1e-300)
+                assert np.array_equal(sim.read_state(i), orc.pack_words(ref.state)), (m, i)
+    for s in sims:
+        s.close()
+
+
 def test_invalid_parameters_rejected():
     lib = B.load()
     bad = [dict(L=100), dict(L=64, cell_log2=6), dict(L=1024, p=1.5), dict(L=1024, subsweeps=3),
