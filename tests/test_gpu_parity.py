@@ -267,6 +267,13 @@ def test_hbm_ring_2p21(orc):
     compare(orc, dict(L=1 << 21, p=1.0, q=0.0, seed=2, stream=5), [0, 1, 3], 1)
 
 
+def test_largest_served_ring(orc):
+    # the longest ring of the served mix: 2^26 sites (2^20 words, 8 MiB per
+    # ring), automatic windows, random start so the heights are large
+    kw = dict(L=1 << 26, p=0.8, q=0.2, init=1, density=0.5, seed=3, stream=9)
+    compare(orc, kw, [0, 1, 2], 1)
+
+
 def test_run_batch_equals_alone(orc):
     kws = [dict(L=4096, p=1.0, q=0.0, seed=1, stream=0), dict(L=4096, p=0.5, q=0.5, seed=1, stream=1),
            dict(L=65536, p=1.0, q=0.0, seed=2, stream=2, windows=2, window_sweeps=17)]
