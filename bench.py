@@ -51,9 +51,9 @@ UPDATE_SLOTS = 10
 # only for the kernel sources they were taken on (SHA-256 prefix below) and
 # for that launch shape; otherwise the bench reports traffic as unknown.
 SWEEP_TRAFFIC = {
-    "src_sha256": "04c688485efbd76c",
+    "src_sha256": "5c656c54d99ef877",
     "launch_shape": {"windows": 4, "window_sweeps": 255, "rings_per_wg": 0},
-    "fetch_kib": 841.25,   # KPZ 839.7, EW 842.8
+    "fetch_kib": 840.48,   # KPZ 839.7, EW 841.25
     "write_kib": 1032.0,
     "fetch_scale": 2.0,    # 4 GiB copy: FETCH_SIZE 2097206 KiB
     "write_scale": 1.0,    # 4 GiB copy: WRITE_SIZE 4194304 KiB

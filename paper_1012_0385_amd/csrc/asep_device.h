@@ -1209,7 +1209,8 @@ inline hipError_t launch_c(const SweepKernel& k, const SimDesc& one, const SimDe
         launch_one<MODEL, C, kGeneric, false>(one, descs, n_desc, grid, block, lds, st, ev0, ev1);
         return hipSuccess;
     }
-    if constexpr (C <= 8) {
+    // two lanes hold twice the state: their specialised loops stop at 8 slots
+    if constexpr (MODEL != kTwoLane || C <= 8) {
         if constexpr (MODEL == kTwoLane) {
             switch (k.variant) {
                 case kF4B0: launch_one<MODEL, C, kF4B0, false>(one, descs, n_desc, grid, block, lds, st, ev0, ev1); return hipSuccess;
@@ -1221,7 +1222,12 @@ inline hipError_t launch_c(const SweepKernel& k, const SimDesc& one, const SimDe
                 case kF5B0: launch_q<MODEL, C, kF5B0>(k, one, descs, n_desc, grid, block, lds, st, ev0, ev1); return hipSuccess;
                 case kF4B1: launch_q<MODEL, C, kF4B1>(k, one, descs, n_desc, grid, block, lds, st, ev0, ev1); return hipSuccess;
                 case kF4B2: launch_q<MODEL, C, kF4B2>(k, one, descs, n_desc, grid, block, lds, st, ev0, ev1); return hipSuccess;
-                case kF1: launch_q<MODEL, C, kF1>(k, one, descs, n_desc, grid, block, lds, st, ev0, ev1); return hipSuccess;
+                case kF1:
+                    if constexpr (C <= 8) {
+                        launch_q<MODEL, C, kF1>(k, one, descs, n_desc, grid, block, lds, st, ev0, ev1);
+                        return hipSuccess;
+                    }
+                    return hipErrorInvalidValue;
                 default: return hipErrorInvalidValue;
             }
         }
@@ -1252,9 +1258,9 @@ inline bool variant_compiled(uint32_t C, uint32_t model, uint32_t variant) {
     if (C != 1 && C != 2 && C != 4 && C != 8 && C != 16) return false;
     if (variant == kGeneric) return true;
     if (variant == kSca) return model != kTwoLane || C <= 8;
-    if (C > 8) return false;
-    if (model == kTwoLane) return variant == kF4B0 || variant == kF1;
-    return variant == kF5B0 || variant == kF4B1 || variant == kF4B2 || variant == kF1;
+    if (model == kTwoLane) return C <= 8 && (variant == kF4B0 || variant == kF1);
+    if (variant == kF1) return C <= 8;  // one field per draw: 16 slots would spill
+    return variant == kF5B0 || variant == kF4B1 || variant == kF4B2;
 }
 
 }  // namespace dev
