@@ -230,6 +230,27 @@ def test_largest_register_ring(orc):
     compare(orc, dict(L=1 << 19, p=1.0, q=0.0, seed=2, stream=5), [0, 2], 1)
 
 
+@pytest.mark.parametrize("kw", [
+    dict(p=0.5, q=0.5),                                   # 4 fields, one compared bit
+    dict(p=0.75, q=0.25, init=1, density=0.4),            # 4 fields, two compared bits
+    dict(p=1.0, q=0.0, slow_frac=0.1, slow_factor=0.5),   # disorder, outcome bits with marks
+    dict(p=0.8, q=0.1, init=1),                           # general rates: the generic loop
+])
+def test_sixteen_slot_loops(orc, kw):
+    # whole rings of 2^19 sites hold 16 slots per lane: the packed attempt
+    # loops with measurements inside the launch, then without (a bare sweep)
+    kw = dict(L=1 << 19, seed=2, stream=6, windows=1, **kw)
+    compare(orc, kw, [0, 1, 3], 2)
+    sim = A.Simulation(A.make_params(samples=2, **kw))
+    sim.sweep(2)
+    OP = oracle_params(orc, kw)
+    for i in range(2):
+        st = orc.init_state(OP, i)
+        orc.advance(OP, i, st, 0, 2)
+        assert np.array_equal(sim.read_state(i), orc.pack_words(st)), i
+    sim.close()
+
+
 # --------------------------------------------------------------------------- windows (HBM tier)
 @pytest.mark.parametrize("L,windows,K,S,p,q", [
     (4096, 2, 3, 4, 1.0, 0.0),     # 64 words in 2 windows, 3 sub-sweeps per launch
