@@ -51,7 +51,7 @@ UPDATE_SLOTS = 10
 # only for the kernel sources they were taken on (SHA-256 prefix below) and
 # for that launch shape; otherwise the bench reports traffic as unknown.
 SWEEP_TRAFFIC = {
-    "src_sha256": "5c656c54d99ef877",
+    "src_sha256": "6ccf0d3e687eaae0",
     "launch_shape": {"windows": 4, "window_sweeps": 255, "rings_per_wg": 0},
     "fetch_kib": 840.48,   # KPZ 839.7, EW 841.25
     "write_kib": 1032.0,

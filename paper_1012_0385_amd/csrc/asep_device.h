@@ -1158,9 +1158,11 @@ inline void launch_one(const SimDesc& one, const SimDesc* descs, uint32_t n_desc
             return;
         }
     }
-    // one ring per wave: windows, or whole rings of whole waves; the
-    // dispatch records the kernel's own start and end in ev0 / ev1 if given
-    const bool wu = one.segs > 1 || one.lanes_per_ring % 64u == 0;
+    // one ring per wave: windows, whole rings of whole waves, or one whole
+    // ring per workgroup (the lanes past it belong to no ring); the dispatch
+    // records the kernel's own start and end in ev0 / ev1 if given
+    const bool wu = one.segs > 1 || one.lanes_per_ring % 64u == 0 ||
+                    (one.rings_per_wg == 1 && one.lanes_per_ring > 64u);
     if (meas) {
         if (wu)
             hipExtLaunchKernelGGL((k_sweep<C, MODEL, V, Q, true, true>), dim3(grid), dim3(block),

@@ -87,6 +87,19 @@ def test_plain_shapes(orc, L, cell_log2, S, p, q):
                       init=1, density=0.4), [0, 1, 5, 12], 3)
 
 
+@pytest.mark.parametrize("kw", [
+    dict(L=64000, p=1.0, q=0.0),                                        # 1000 lanes
+    dict(L=64000, p=0.5, q=0.5, init=1, density=0.4),
+    dict(L=64000, p=1.0, q=0.0, slow_frac=0.1, slow_factor=0.5),
+    dict(L=64000, model=1, init=1, density=0.3, p=1.0, q=1.0, lane_rate=0.1, turn_frac=0.05),
+    dict(L=96000, p=0.75, q=0.25, init=1),                              # 2 slots, 750 lanes
+])
+def test_whole_ring_partial_last_wave(orc, kw):
+    # one ring per workgroup whose lanes end inside a wave: the last wave's
+    # remaining lanes belong to no ring, so every wave still serves one ring
+    compare(orc, dict(seed=8, stream=4, windows=1, **kw), [0, 1, 6, 13], 2)
+
+
 def test_many_rings_per_workgroup(orc):
     # 37 rings of 2 words: packed 128 per workgroup, last workgroup partial
     compare(orc, dict(L=128, p=0.8, q=0.3, seed=5, stream=9), [0, 3, 40], 37)
