@@ -308,6 +308,28 @@ def test_largest_served_ring(orc):
     compare(orc, kw, [0, 1, 2], 1)
 
 
+@pytest.mark.parametrize("shape", [dict(windows=1), dict(windows=2, window_sweeps=7)])
+@pytest.mark.parametrize("kw", [
+    dict(init=1, density=0.0, p=0.7, q=0.3),                    # empty ring
+    dict(init=1, density=1.0, p=0.7, q=0.3),                    # full ring
+    dict(init=1, density=0.5, p=0.0, q=0.0),                    # no hops at all
+    dict(init=1, density=0.4, p=0.0, q=0.0, slow_frac=0.5, slow_factor=0.5),
+    dict(model=1, init=1, density=0.0, p=1.0, q=1.0, lane_rate=0.1, turn_frac=0.05),
+])
+def test_degenerate_cases(orc, kw, shape):
+    # nothing can move: every record equals the oracle's, no hop is counted,
+    # and the final words are the initial ones
+    kw = dict(L=8192, seed=4, stream=11, **kw, **shape)
+    got = compare(orc, kw, [0, 2, 9], 2)
+    assert all(int(j) == 0 for r in got for j in r.J)
+    OP = oracle_params(orc, kw)
+    sim = A.Simulation(A.make_params(samples=2, **kw))
+    sim.sweep(9)
+    for i in range(2):
+        assert np.array_equal(sim.read_state(i), orc.pack_words(orc.init_state(OP, i))), i
+    sim.close()
+
+
 def test_run_batch_equals_alone(orc):
     kws = [dict(L=4096, p=1.0, q=0.0, seed=1, stream=0), dict(L=4096, p=0.5, q=0.5, seed=1, stream=1),
            dict(L=65536, p=1.0, q=0.0, seed=2, stream=2, windows=2, window_sweeps=17)]
