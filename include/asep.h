@@ -49,7 +49,7 @@
 extern "C" {
 #endif
 
-#define ASEP_ABI_VERSION 2u
+#define ASEP_ABI_VERSION 3u
 
 enum {
     ASEP_OK = 0,
@@ -68,7 +68,8 @@ enum { ASEP_MODEL_RING = 0, ASEP_MODEL_TWO_LANE = 1 };
 enum { ASEP_INIT_FLAT = 0, ASEP_INIT_BERNOULLI = 1 };
 enum { ASEP_SCHED_SHIFTED = 0, ASEP_SCHED_SUBLATTICE = 1 };
 
-/* Run parameters.  Zero-initialise, then set abi_version = ASEP_ABI_VERSION. */
+/* Run parameters.  Zero-initialise, then set abi_version = ASEP_ABI_VERSION
+ * and the fields of the run; every field left at zero takes its default. */
 typedef struct asep_params {
     uint32_t abi_version;
     uint32_t model;    /* ASEP_MODEL_RING | ASEP_MODEL_TWO_LANE */
@@ -92,17 +93,23 @@ typedef struct asep_params {
     double turn_frac;  /* two lanes: fraction of turning points, [0,1] */
     uint32_t seed;     /* Philox key word 0 */
     uint32_t stream;   /* Philox key word 1 (the caller's request identity) */
-    int32_t cell_log2; /* ell = 2^cell_log2 in [1,6]; 0 = default (6) */
-    int32_t subsweeps; /* S, dividing ell (two lanes: 4 ell); 0 = default (4) */
+    int32_t cell_log2; /* ell = 2^cell_log2 in [1,6]; 0 = from the tuning table
+                          (asep_tuning_load) if an entry matches, else 6 */
+    int32_t subsweeps; /* S, dividing ell (two lanes: 4 ell); 0 = from the
+                          tuning table if an entry matches, else 4 */
     int32_t rbits;     /* bits compared against each acceptance threshold:
-                          -1 = the fewest that keep every threshold exact,
-                          else an explicit count (ASEP_E_INVAL if inexact) */
-    uint32_t windows;  /* launch shape only, never results: 0 = automatic,
-                          1 = each ring whole in one workgroup, n >= 2 = each
-                          ring cut into n windows (one workgroup each) */
-    uint32_t window_sweeps; /* sub-sweeps per launch of a windowed ring; 0 = 63 */
+                          0 (or negative) = the fewest that keep every threshold
+                          exact, n >= 1 = exactly n (ASEP_E_INVAL if a threshold
+                          is not exact at n bits); an explicit 0 would always
+                          equal the automatic choice, so 0 means automatic */
+    uint32_t windows;  /* launch shape only, never results: 0 = from the tuning
+                          table, else automatic; 1 = each ring whole in one
+                          workgroup, n >= 2 = each ring cut into n windows */
+    uint32_t window_sweeps; /* sub-sweeps per launch of a windowed ring; 0 = from
+                               the tuning table, else 63 */
     uint32_t rings_per_wg;  /* launch shape only: whole rings packed per
-                               workgroup; 0 = automatic */
+                               workgroup; 0 = from the tuning table, else
+                               automatic */
     uint32_t schedule; /* ASEP_SCHED_SHIFTED (the shifted cells above) or
                           ASEP_SCHED_SUBLATTICE, the paper's SCA:
                           rings (Sec. 2.1, Fig. parasep): every pair (x, x+1)
@@ -155,8 +162,45 @@ int asep_create(const asep_params* p, asep_sim** out);
 int asep_create_ext(const asep_params* p, void* state_dev, size_t state_bytes, void* aux_dev,
                     size_t aux_bytes, void* hip_stream, asep_sim** out);
 
-/* Parameters as resolved at creation (defaults filled in). */
+/* Parameters as resolved at creation: defaults and tuning-table values
+ * filled in (cell_log2, subsweeps, rbits, samples_per_disorder, and the
+ * launch-shape fields as used). */
 int asep_get_params(const asep_sim* s, asep_params* out);
+
+/* Launch plan of a simulation: how its rings are laid out on the device
+ * (Sec. 2.1: independent rings per block, one ring held on chip; Sec. 2.4:
+ * rings longer than on-chip memory pass through device memory).  The plan is
+ * launch shape only and never changes a result. */
+enum {
+    ASEP_LOOP_GENERIC = 0,   /* any cell size and attempt count */
+    ASEP_LOOP_F5B0 = 1,      /* ell = 64, 16 attempts: 5 per 32-bit draw, no compared bit */
+    ASEP_LOOP_F4B1 = 2,      /* 4 per draw, 1 compared bit */
+    ASEP_LOOP_F4B2 = 3,      /* 4 per draw, 2 compared bits */
+    ASEP_LOOP_F1 = 4,        /* 1 per draw, compared bits at run time */
+    ASEP_LOOP_F4B0_LANES = 5,/* two lanes, 64 attempts: 4 per draw, no compared bit */
+    ASEP_LOOP_SUBLATTICE = 6 /* the paper's two-sub-lattice update */
+};
+typedef struct asep_plan {
+    uint32_t windows;        /* 1: each ring whole in one workgroup; n >= 2: windows per ring */
+    uint32_t window_sweeps;  /* sub-sweeps per launch of a windowed ring (0: whole rings) */
+    uint32_t slots_per_lane; /* 64-site words held by each lane: 1, 2, 4, 8 or 16 */
+    uint32_t block;          /* lanes per workgroup */
+    uint32_t lanes_per_ring; /* lanes serving one ring (whole rings) or one window */
+    uint32_t rings_per_wg;   /* whole rings per workgroup */
+    uint32_t grid;           /* workgroups per sweep launch */
+    uint32_t attempt_loop;   /* ASEP_LOOP_* */
+    uint32_t backward_hops;  /* 0 when no backward hop can happen (q = 0 and r q = 0) */
+    uint32_t packable;       /* 1 when the request loop may share a launch with others */
+    uint32_t reserved[6];
+} asep_plan;
+int asep_get_plan(const asep_sim* s, asep_plan* out);
+
+/* What asep_create would resolve, without creating anything (host only, no
+ * device memory or work): *resolved receives the parameters with defaults
+ * and tuning-table values filled in, *plan (may be NULL) the launch plan for
+ * the current HIP device (gfx950's limits if none is visible).  Same
+ * validation and error codes as asep_create. */
+int asep_resolve(const asep_params* p, asep_params* resolved, asep_plan* plan);
 
 /* Advance every sample by n_mcs Monte Carlo steps; asynchronous on the
  * simulation's stream.  Splitting n_mcs into several calls gives bit-identical
@@ -252,7 +296,11 @@ typedef struct asep_server_cfg {
     uint32_t max_queue;        /* pending requests before ASEP_E_BUSY */
     uint32_t max_active;       /* requests resident at once */
     uint64_t quantum_mcs;      /* MCS a resident request advances per round
-                                  (0: 1000; at most 2^28, larger values are capped) */
+                                  (0: 1000); a whole-ring request's quantum is
+                                  further cut to one launch (2^30 sub-sweeps) */
+    const char* tuning_path;   /* tuning table loaded at creation with
+                                  asep_tuning_load; NULL: the process's table
+                                  as it is */
     uint32_t reserved[4];
 } asep_server_cfg;
 
@@ -271,9 +319,28 @@ typedef struct asep_result {
     asep_rough* rough;      /* [n_times * samples], time-major */
     uint64_t t_arrive_ns, t_admit_ns, t_start_ns, t_done_ns; /* CLOCK_MONOTONIC */
     uint64_t site_updates;  /* elementary attempts performed */
+    asep_params params;     /* the request's parameters as resolved (the
+                               schedule used: cell size, sub-sweeps, compared
+                               bits); zero if it never became resident */
+    asep_plan plan;         /* launch plan of its rings (zero likewise) */
+    uint32_t quanta;        /* work segments it was advanced in */
+    uint32_t packed_quanta; /* of those, the ones that shared a launch */
 } asep_result;
 
 typedef struct asep_server asep_server;
+
+/* Tuning table: launch shapes and, optionally, the update schedule (cell
+ * size, sub-sweeps per MCS) chosen by the autotuner per class of run.  Text,
+ * one entry per line, '#' comments:
+ *   model schedule disorder log2L_min log2L_max samples_min samples_max
+ *   cell_log2 subsweeps windows window_sweeps rings_per_wg
+ * (disorder: 1 if slow_frac > 0; L and samples ranges inclusive; a value 0
+ * leaves that field to its default).  asep_create and asep_buffer_sizes fill
+ * every parameter left at 0 from the first matching entry.  The table is
+ * process-wide: loading replaces it, NULL or "" clears it.  ASEP_E_INVAL on a
+ * malformed line (the table in use is then unchanged), ASEP_E_NOTFOUND if the
+ * file cannot be read. */
+int asep_tuning_load(const char* path);
 
 int asep_server_create(const asep_server_cfg* cfg, asep_server** out);
 void asep_server_destroy(asep_server* s);

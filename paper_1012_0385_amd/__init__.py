@@ -7,6 +7,8 @@ and fails loudly if the library has not been built.
 """
 from . import binding
 from .binding import AsepError
-from .sim import Server, Simulation, ensemble_w2, make_params, run_batch, sample_times
+from .sim import (Server, Simulation, ensemble_w2, load_tuning, make_params, resolve,
+                  run_batch, sample_times)
 
-__all__ = ["binding", "AsepError", "Server", "Simulation", "ensemble_w2", "make_params", "run_batch", "sample_times"]
+__all__ = ["binding", "AsepError", "Server", "Simulation", "ensemble_w2", "load_tuning",
+           "make_params", "resolve", "run_batch", "sample_times"]

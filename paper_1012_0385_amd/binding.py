@@ -13,7 +13,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libasep.so")
 
-ASEP_ABI_VERSION = 2
+ASEP_ABI_VERSION = 3
 ASEP_OK = 0
 ASEP_E_INVAL = -1
 ASEP_E_UNSUPPORTED = -2
@@ -30,6 +30,13 @@ ASEP_INIT_FLAT = 0
 ASEP_INIT_BERNOULLI = 1
 ASEP_SCHED_SHIFTED = 0
 ASEP_SCHED_SUBLATTICE = 1
+ASEP_LOOP_GENERIC = 0
+ASEP_LOOP_F5B0 = 1
+ASEP_LOOP_F4B1 = 2
+ASEP_LOOP_F4B2 = 3
+ASEP_LOOP_F1 = 4
+ASEP_LOOP_F4B0_LANES = 5
+ASEP_LOOP_SUBLATTICE = 6
 
 
 class asep_params(ctypes.Structure):
@@ -71,6 +78,22 @@ class asep_rough(ctypes.Structure):
     ]
 
 
+class asep_plan(ctypes.Structure):
+    _fields_ = [
+        ("windows", ctypes.c_uint32),
+        ("window_sweeps", ctypes.c_uint32),
+        ("slots_per_lane", ctypes.c_uint32),
+        ("block", ctypes.c_uint32),
+        ("lanes_per_ring", ctypes.c_uint32),
+        ("rings_per_wg", ctypes.c_uint32),
+        ("grid", ctypes.c_uint32),
+        ("attempt_loop", ctypes.c_uint32),
+        ("backward_hops", ctypes.c_uint32),
+        ("packable", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32 * 6),
+    ]
+
+
 class asep_profile_stats(ctypes.Structure):
     _fields_ = [
         ("launches", ctypes.c_uint64),
@@ -87,6 +110,7 @@ class asep_server_cfg(ctypes.Structure):
         ("max_queue", ctypes.c_uint32),
         ("max_active", ctypes.c_uint32),
         ("quantum_mcs", ctypes.c_uint64),
+        ("tuning_path", ctypes.c_char_p),
         ("reserved", ctypes.c_uint32 * 4),
     ]
 
@@ -112,6 +136,10 @@ class asep_result(ctypes.Structure):
         ("t_start_ns", ctypes.c_uint64),
         ("t_done_ns", ctypes.c_uint64),
         ("site_updates", ctypes.c_uint64),
+        ("params", asep_params),
+        ("plan", asep_plan),
+        ("quanta", ctypes.c_uint32),
+        ("packed_quanta", ctypes.c_uint32),
     ]
 
 
@@ -128,6 +156,8 @@ SIGNATURES = {
     "asep_create": (_i32, [_P(asep_params), _P(_vp)]),
     "asep_create_ext": (_i32, [_P(asep_params), _vp, _sz, _vp, _sz, _vp, _P(_vp)]),
     "asep_get_params": (_i32, [_vp, _P(asep_params)]),
+    "asep_get_plan": (_i32, [_vp, _P(asep_plan)]),
+    "asep_resolve": (_i32, [_P(asep_params), _P(asep_params), _P(asep_plan)]),
     "asep_sweep": (_i32, [_vp, _u64]),
     "asep_roughness": (_i32, [_vp, _P(asep_rough)]),
     "asep_run": (_i32, [_vp, _P(_u64), _u32, _P(asep_rough)]),
@@ -147,6 +177,7 @@ SIGNATURES = {
                                  _P(_u32)]),
     "asep_strerror": (ctypes.c_char_p, [_i32]),
     "asep_last_device_error": (ctypes.c_char_p, []),
+    "asep_tuning_load": (_i32, [ctypes.c_char_p]),
     "asep_server_create": (_i32, [_P(asep_server_cfg), _P(_vp)]),
     "asep_server_destroy": (None, [_vp]),
     "asep_submit": (_i32, [_vp, _P(asep_request), _P(_u64)]),

@@ -35,8 +35,21 @@ def _flags():
     ]
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source of the library and link libasep.so (always rebuilds)."""
+HEADERS = [os.path.join(CSRC, h) for h in ("asep_device.h", "asep_internal.h", "asep_serve.h")] + [
+    os.path.join(ROOT, "include", "asep.h")]
+
+
+def _stale(path: str, obj: str) -> bool:
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    return any(os.path.getmtime(f) > t for f in [path] + HEADERS if os.path.exists(f))
+
+
+def build(verbose: bool = False, incremental: bool = False) -> str:
+    """Compile every source of the library and link libasep.so.  By default
+    everything is recompiled; with incremental=True only objects older than
+    their source or a shared header are."""
     cc = hipcc()
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
@@ -47,6 +60,9 @@ def build(verbose: bool = False) -> str:
         if not os.path.exists(path):
             continue
         obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
+        if incremental and not _stale(path, obj):
+            objs.append(obj)
+            continue
         cmd = [cc] + _flags() + ["-c", path, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
@@ -64,4 +80,6 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    import sys
+
+    print(build(verbose=True, incremental="--incremental" in sys.argv))

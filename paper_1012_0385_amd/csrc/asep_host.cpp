@@ -8,7 +8,11 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
 #include <new>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -48,6 +52,90 @@ bool in01(double x) { return x >= 0.0 && x <= 1.0; }
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Tuning table (process-wide): per class of run (model, schedule, disorder,
+// range of log2 L, range of samples) the launch shape and, for the shifted
+// schedule, the cell size and sub-sweeps the autotuner chose.  Parameters
+// left at 0 are filled from the first matching entry.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct TuneEntry {
+    uint32_t model, schedule, disorder;
+    uint32_t l2_lo, l2_hi;
+    uint64_t s_lo, s_hi;
+    int32_t cell_log2, subsweeps;
+    uint32_t windows, window_sweeps, rings_per_wg;
+};
+
+std::mutex g_tune_mu;
+std::vector<TuneEntry> g_tune;
+
+uint32_t floor_log2(uint64_t v) {
+    uint32_t e = 0;
+    while (v >>= 1) ++e;
+    return e;
+}
+
+bool tune_match(const asep_params& P, TuneEntry* out) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    const uint32_t e = floor_log2(P.L);
+    const uint32_t dis = P.slow_frac > 0 ? 1u : 0u;
+    for (const TuneEntry& t : g_tune) {
+        if (t.model == P.model && t.schedule == P.schedule && t.disorder == dis && e >= t.l2_lo &&
+            e <= t.l2_hi && P.samples >= t.s_lo && P.samples <= t.s_hi) {
+            *out = t;
+            return true;
+        }
+    }
+    return false;
+}
+
+}  // namespace
+
+extern "C" int asep_tuning_load(const char* path) {
+    std::vector<TuneEntry> tab;
+    if (path && *path) {
+        std::ifstream f(path);
+        if (!f) return ASEP_E_NOTFOUND;
+        std::string line;
+        while (std::getline(f, line)) {
+            const size_t h = line.find('#');
+            if (h != std::string::npos) line.resize(h);
+            std::istringstream in(line);
+            TuneEntry t{};
+            long long v[12];
+            int n = 0;
+            while (n < 12 && (in >> v[n])) ++n;
+            if (n == 0 && in.eof()) continue;  // blank or comment
+            std::string rest;
+            if (n != 12 || (in >> rest)) return ASEP_E_INVAL;
+            for (int i = 0; i < 12; ++i)
+                if (v[i] < 0 || v[i] > 0xFFFFFFFFll) return ASEP_E_INVAL;
+            t.model = (uint32_t)v[0];
+            t.schedule = (uint32_t)v[1];
+            t.disorder = (uint32_t)v[2];
+            t.l2_lo = (uint32_t)v[3];
+            t.l2_hi = (uint32_t)v[4];
+            t.s_lo = (uint64_t)v[5];
+            t.s_hi = (uint64_t)v[6];
+            t.cell_log2 = (int32_t)v[7];
+            t.subsweeps = (int32_t)v[8];
+            t.windows = (uint32_t)v[9];
+            t.window_sweeps = (uint32_t)v[10];
+            t.rings_per_wg = (uint32_t)v[11];
+            if (t.model > 1 || t.schedule > 1 || t.disorder > 1 || t.l2_lo > t.l2_hi ||
+                t.l2_hi > 63 || t.s_lo > t.s_hi || t.cell_log2 > 6 || t.subsweeps > 256 ||
+                t.window_sweeps > 4096)
+                return ASEP_E_INVAL;
+            tab.push_back(t);
+        }
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.swap(tab);
+    return ASEP_OK;
+}
+
 // Resolved parameters plus the lowered schedule.
 struct Resolved {
     asep_params P;
@@ -61,15 +149,31 @@ struct Resolved {
     uint32_t real0;       // first realisation
     uint32_t spd;
     uint32_t model;       // kernel model
+    int dev;              // device whose limits the plan follows
 };
 
-static int resolve(const asep_params* in, Resolved* r) {
+static int resolve(const asep_params* in, int dev, Resolved* r) {
     if (!in) return ASEP_E_INVAL;
     if (in->abi_version != ASEP_ABI_VERSION) return ASEP_E_INVAL;
     asep_params P = *in;
     if (P.schedule != ASEP_SCHED_SHIFTED && P.schedule != ASEP_SCHED_SUBLATTICE)
         return ASEP_E_INVAL;
     const bool sca = P.schedule == ASEP_SCHED_SUBLATTICE;
+    // parameters left at 0 take the tuning table's values: the update
+    // schedule (shifted cells only) as one unit when neither is given, the
+    // launch shape as one unit when none of its fields is given
+    TuneEntry te;
+    if (P.samples && tune_match(P, &te)) {
+        if (!sca && P.cell_log2 == 0 && P.subsweeps == 0 && te.cell_log2 && te.subsweeps) {
+            P.cell_log2 = te.cell_log2;
+            P.subsweeps = te.subsweeps;
+        }
+        if (P.windows == 0 && P.window_sweeps == 0 && P.rings_per_wg == 0) {
+            P.windows = te.windows;
+            P.window_sweeps = te.window_sweeps;
+            P.rings_per_wg = te.rings_per_wg;
+        }
+    }
     if (sca) {
         // pairs of two sites; single lane: even pairs, odd pairs (S = 2);
         // two lanes: even pairs, A -> B, odd pairs, B -> A (S = 4)
@@ -138,7 +242,7 @@ static int resolve(const asep_params* in, Resolved* r) {
         return true;
     };
     int b;
-    if (P.rbits < 0) {
+    if (P.rbits <= 0) {
         for (b = 0; b < B && !exact_at(b); ++b) {
         }
     } else {
@@ -165,6 +269,7 @@ static int resolve(const asep_params* in, Resolved* r) {
 
     r->P = P;
     r->sc = sc;
+    r->dev = dev;
     r->planes = two ? 2 : 1;
     r->nw = (uint32_t)(P.L / 64);
     r->spd = P.samples_per_disorder;
@@ -217,21 +322,35 @@ struct Plan {
     SweepKernel kern{};
 };
 
-static void device_limits(size_t* lds, uint32_t* cus) {
-    static size_t lim = 0;
-    static uint32_t ncu = 0;
-    if (!lim) {
-        int dev = 0;
+// LDS per workgroup and compute units of a device, looked up once per
+// device (any thread may plan: the request loop sizes requests on the
+// submitting thread).
+static void device_limits(int dev, size_t* lds, uint32_t* cus) {
+    static std::mutex mu;
+    static std::map<int, std::pair<size_t, uint32_t>> cache;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(dev);
+    if (it == cache.end()) {
+        size_t lim = 0;
+        uint32_t ncu = 0;
         hipDeviceProp_t prop;
-        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        if (dev >= 0 && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
             lim = prop.sharedMemPerBlock;
             ncu = (uint32_t)prop.multiProcessorCount;
         }
-        if (!lim) lim = 65536;
+        // no device visible (host-only planning): gfx950's limits
+        if (!lim) lim = 160 * 1024;
         if (!ncu) ncu = 256;
+        it = cache.emplace(dev, std::make_pair(lim, ncu)).first;
     }
-    *lds = lim;
-    *cus = ncu;
+    *lds = it->second.first;
+    *cus = it->second.second;
+}
+
+static int current_device() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    return dev;
 }
 
 // Attempt-loop variant: the specialised ones need ell = 64 and the default
@@ -266,7 +385,7 @@ static SweepKernel pick_kernel(const Resolved& r, uint32_t C) {
 static bool plan_whole(const Resolved& r, Plan* p) {
     size_t lim;
     uint32_t ncu;
-    device_limits(&lim, &ncu);
+    device_limits(r.dev, &lim, &ncu);
     const uint32_t nw = r.nw, R = r.P.samples;
     static const uint32_t Cs[] = {1, 2, 4, 8, 16};
     for (uint32_t C : Cs) {
@@ -308,7 +427,7 @@ static bool plan_whole(const Resolved& r, Plan* p) {
 static bool plan_windows(const Resolved& r, uint32_t segs, uint32_t K, Plan* p) {
     size_t lim;
     uint32_t ncu;
-    device_limits(&lim, &ncu);
+    device_limits(r.dev, &lim, &ncu);
     const uint32_t nw = r.nw;
     if (segs < 2 || segs > nw) return false;
     const uint32_t seg_n = (nw + segs - 1) / segs;
@@ -349,7 +468,7 @@ static bool plan_windows(const Resolved& r, uint32_t segs, uint32_t K, Plan* p) 
 static int choose_plan(const Resolved& r, Plan* p) {
     size_t lim;
     uint32_t ncu;
-    device_limits(&lim, &ncu);
+    device_limits(r.dev, &lim, &ncu);
     const uint32_t want = r.P.windows;  // windows per ring (0 = auto)
     uint32_t K = r.P.window_sweeps ? r.P.window_sweeps : 63;  // sub-sweeps per window launch
     if (K > 4096) return ASEP_E_INVAL;
@@ -393,6 +512,7 @@ struct asep_sim {
     void* own_aux = nullptr;
     uint64_t t = 0;
     Record* host_rec = nullptr;  // pinned staging of rec_cap x samples records
+    bool own_host_rec = false;   // allocated here (else borrowed from the caller)
     // sweep-launch timing
     bool prof = false;
     std::vector<hipEvent_t> ev;    // pairs (start, stop), ring buffer
@@ -441,9 +561,10 @@ static void aux_layout(const Resolved& r, const Plan& pl, size_t* o_masks, size_
     *total = (off + 255) & ~(size_t)255;
 }
 
-extern "C" int asep_buffer_sizes(const asep_params* p, size_t* state_bytes, size_t* aux_bytes) {
+static int buffer_sizes_on(const asep_params* p, int dev, size_t* state_bytes,
+                           size_t* aux_bytes) {
     Resolved r;
-    int rc = resolve(p, &r);
+    int rc = resolve(p, dev, &r);
     if (rc) return rc;
     Plan pl;
     rc = choose_plan(r, &pl);
@@ -453,6 +574,10 @@ extern "C" int asep_buffer_sizes(const asep_params* p, size_t* state_bytes, size
     if (state_bytes) *state_bytes = (size_t)r.P.samples * r.planes * r.nw * 8;
     if (aux_bytes) *aux_bytes = tot;
     return ASEP_OK;
+}
+
+extern "C" int asep_buffer_sizes(const asep_params* p, size_t* state_bytes, size_t* aux_bytes) {
+    return buffer_sizes_on(p, current_device(), state_bytes, aux_bytes);
 }
 
 static int sim_init(asep_sim* s) {
@@ -467,11 +592,12 @@ static int sim_init(asep_sim* s) {
 }
 
 static int create_common(const asep_params* p, void* state, size_t state_bytes, void* aux,
-                         size_t aux_bytes, void* stream, bool borrowed, asep_sim** out) {
+                         size_t aux_bytes, void* stream, bool borrowed, Record* host_rec,
+                         asep_sim** out) {
     if (!out) return ASEP_E_INVAL;
     asep_sim* s = new (std::nothrow) asep_sim();
     if (!s) return ASEP_E_NOMEM;
-    int rc = resolve(p, &s->r);
+    int rc = resolve(p, current_device(), &s->r);
     if (rc == ASEP_OK) rc = choose_plan(s->r, &s->plan);
     if (rc) {
         delete s;
@@ -507,11 +633,15 @@ static int create_common(const asep_params* p, void* state, size_t state_bytes, 
     s->hops = (int64_t*)(a + o_hops);
     s->rec = (Record*)(a + o_rec);
     (void)o_recg;
-    if (hipHostMalloc((void**)&s->host_rec, sizeof(Record) * (size_t)kRecCap * s->r.P.samples) !=
-        hipSuccess) {
+    if (host_rec) {
+        s->host_rec = host_rec;  // borrowed pinned staging
+    } else if (hipHostMalloc((void**)&s->host_rec,
+                             sizeof(Record) * (size_t)kRecCap * s->r.P.samples) != hipSuccess) {
         s->host_rec = nullptr;
         asep_destroy(s);
         return ASEP_E_NOMEM;
+    } else {
+        s->own_host_rec = true;
     }
     s->alt = s->plan.seg ? (uint64_t*)(a + o_alt) : nullptr;
     s->rec_cap = kRecCap;
@@ -525,13 +655,14 @@ static int create_common(const asep_params* p, void* state, size_t state_bytes, 
 }
 
 extern "C" int asep_create(const asep_params* p, asep_sim** out) {
-    return create_common(p, nullptr, 0, nullptr, 0, nullptr, false, out);
+    return create_common(p, nullptr, 0, nullptr, 0, nullptr, false, nullptr, out);
 }
 
 extern "C" int asep_create_ext(const asep_params* p, void* state_dev, size_t state_bytes,
                                void* aux_dev, size_t aux_bytes, void* hip_stream,
                                asep_sim** out) {
-    return create_common(p, state_dev, state_bytes, aux_dev, aux_bytes, hip_stream, true, out);
+    return create_common(p, state_dev, state_bytes, aux_dev, aux_bytes, hip_stream, true,
+                         nullptr, out);
 }
 
 extern "C" int asep_get_params(const asep_sim* s, asep_params* out) {
@@ -540,11 +671,44 @@ extern "C" int asep_get_params(const asep_sim* s, asep_params* out) {
     return ASEP_OK;
 }
 
+static void fill_plan(const Plan& pl, asep_plan* o) {
+    std::memset(o, 0, sizeof *o);
+    o->windows = pl.seg ? pl.segs : 1;
+    o->window_sweeps = pl.seg ? pl.K : 0;
+    o->slots_per_lane = pl.kern.C;
+    o->block = pl.block;
+    o->lanes_per_ring = pl.lanes_per_ring;
+    o->rings_per_wg = pl.rings_per_wg;
+    o->grid = pl.grid;
+    o->attempt_loop = pl.kern.variant;
+    o->backward_hops = pl.kern.q0 ? 0u : 1u;
+    o->packable = (!pl.seg && pl.kern.C <= 4) ? 1u : 0u;
+}
+
+extern "C" int asep_get_plan(const asep_sim* s, asep_plan* out) {
+    if (!s || !out) return ASEP_E_INVAL;
+    fill_plan(s->plan, out);
+    return ASEP_OK;
+}
+
+extern "C" int asep_resolve(const asep_params* p, asep_params* resolved, asep_plan* plan) {
+    if (!resolved) return ASEP_E_INVAL;
+    Resolved r;
+    int rc = resolve(p, current_device(), &r);
+    if (rc) return rc;
+    Plan pl;
+    rc = choose_plan(r, &pl);
+    if (rc) return rc;
+    *resolved = r.P;
+    if (plan) fill_plan(pl, plan);
+    return ASEP_OK;
+}
+
 extern "C" void asep_destroy(asep_sim* s) {
     if (!s) return;
     // work queued on a borrowed stream is the caller's to wait for
     if (s->own_stream && s->stream) (void)hipStreamSynchronize(s->stream);
-    if (s->host_rec) (void)hipHostFree(s->host_rec);
+    if (s->host_rec && s->own_host_rec) (void)hipHostFree(s->host_rec);
     for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
     if (s->own_state) (void)hipFree(s->own_state);
     if (s->own_aux) (void)hipFree(s->own_aux);
@@ -805,6 +969,35 @@ extern "C" int asep_run_batch(asep_sim* const* sims, uint32_t n_sims, const uint
 namespace asep {
 
 uint32_t sim_record_capacity(const asep_sim* s) { return s->rec_cap; }
+
+size_t sim_host_rec_bytes(const asep_params& p) {
+    return sizeof(Record) * (size_t)kRecCap * p.samples;
+}
+
+int sim_buffer_sizes_on(const asep_params* p, int dev, size_t* state_bytes, size_t* aux_bytes) {
+    return buffer_sizes_on(p, dev, state_bytes, aux_bytes);
+}
+
+// asep_create_ext with a borrowed pinned staging buffer of at least
+// sim_host_rec_bytes(*p) bytes, which the simulation never frees.
+int sim_create_borrowed(const asep_params* p, void* state, size_t state_bytes, void* aux,
+                        size_t aux_bytes, hipStream_t st, Record* host_rec, asep_sim** out) {
+    if (!host_rec) return ASEP_E_INVAL;
+    return create_common(p, state, state_bytes, aux, aux_bytes, st, true, host_rec, out);
+}
+
+// Longest run one quantum of the request loop may take: whole rings may be
+// packed into one launch, whose sub-sweep count is 32 bits wide; windowed
+// rings are cut into launches of K sub-sweeps anyway.
+uint64_t sim_max_quantum_mcs(const asep_sim* s) {
+    if (s->plan.seg) return ~0ull;
+    return std::max<uint64_t>(1, kMaxLaunchSub / s->r.sc.S);
+}
+
+void sim_describe(const asep_sim* s, asep_params* resolved, asep_plan* plan) {
+    *resolved = s->r.P;
+    fill_plan(s->plan, plan);
+}
 hipStream_t sim_stream(const asep_sim* s) { return s->stream; }
 uint32_t sim_samples(const asep_sim* s) { return s->r.P.samples; }
 uint64_t sim_attempts_per_mcs(const asep_sim* s) {

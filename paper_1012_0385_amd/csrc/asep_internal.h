@@ -107,8 +107,16 @@ bool sweep_variant_compiled(uint32_t C, uint32_t model, uint32_t variant);
 // Internal hooks of the host library used by the request loop.
 struct asep_sim;
 struct asep_rough;
+struct asep_params;
+struct asep_plan;
 namespace asep {
 uint32_t sim_record_capacity(const asep_sim* s);
+size_t sim_host_rec_bytes(const asep_params& p);
+int sim_buffer_sizes_on(const asep_params* p, int dev, size_t* state_bytes, size_t* aux_bytes);
+int sim_create_borrowed(const asep_params* p, void* state, size_t state_bytes, void* aux,
+                        size_t aux_bytes, hipStream_t st, Record* host_rec, asep_sim** out);
+uint64_t sim_max_quantum_mcs(const asep_sim* s);
+void sim_describe(const asep_sim* s, asep_params* resolved, asep_plan* plan);
 hipStream_t sim_stream(const asep_sim* s);
 uint32_t sim_samples(const asep_sim* s);
 uint64_t sim_attempts_per_mcs(const asep_sim* s);

@@ -39,11 +39,10 @@ using asep::serve::Job;
 
 struct asep_server {
     asep_server_cfg cfg{};
-    std::mutex mu;
+    std::mutex mu;                    // guards queue, all, stop, ready, init_rc, Job::status
     std::condition_variable cv_work;  // worker waits for requests
     std::condition_variable cv_done;  // clients wait for results
-    std::deque<std::shared_ptr<Job>> queue;
-    std::vector<std::shared_ptr<Job>> active;
+    std::deque<std::shared_ptr<Job>> queue;        // submitted, not yet taken by the worker
     std::map<uint64_t, std::shared_ptr<Job>> all;  // every ticket not yet collected
     uint64_t next_ticket = 1;
     bool stop = false;
@@ -64,105 +63,119 @@ uint64_t now_ns() {
 
 namespace {
 
-void finish(asep_server* S, Job& j, int status) {
-    j.status = status;
-    j.t_done = now_ns();
-    if (j.x) S->X->release(j);
-    j.inflight = false;
-}
+// State of the worker thread only.
+struct Worker {
+    asep_server* S;
+    Executor& X;
+    std::vector<std::shared_ptr<Job>> active;  // resident jobs
+    std::vector<std::shared_ptr<Job>> done;    // concluded, status not yet published
 
-// The job's next quantum: end time and number of measurements in it.
-void next_quantum(asep_server* S, const Job& j, uint64_t* t_end_out, uint32_t* n_out) {
-    const uint64_t t = S->X->time(j);
-    const uint64_t q = std::max<uint64_t>(S->cfg.quantum_mcs, 1);
-    uint64_t t_end = std::min(j.t_max, t + q);
-    const uint32_t cap = S->X->record_capacity(j);
-    uint32_t n = 0;
-    while (j.next_time + n < j.times.size() && j.times[j.next_time + n] <= t_end && n < cap) ++n;
-    if (n == cap && j.next_time + n < j.times.size() && j.times[j.next_time + n] <= t_end)
-        t_end = j.times[j.next_time + n - 1];
-    *t_end_out = t_end;
-    *n_out = n;
-}
-
-void mark_queued(asep_server* S, Job& j, uint64_t t0, uint64_t t_end, uint32_t n) {
-    if (!j.t_start) j.t_start = now_ns();
-    j.updates += (t_end - t0) * S->X->attempts_per_mcs(j);
-    j.staged_first = j.next_time;
-    j.staged_n = n;
-    j.next_time += n;
-    j.inflight = true;
-}
-
-// Queue one quantum of each job of the group (one launch if several);
-// false if the executor cannot take a shared launch now.
-bool queue_group(asep_server* S, const std::vector<Job*>& g,
-                 std::vector<std::pair<Job*, int>>* failed) {
-    std::vector<uint64_t> t_end(g.size()), t0(g.size());
-    std::vector<uint32_t> n(g.size());
-    for (size_t i = 0; i < g.size(); ++i) {
-        next_quantum(S, *g[i], &t_end[i], &n[i]);
-        t0[i] = S->X->time(*g[i]);
+    // The job is over: free its device state (it has no work in flight) and
+    // keep its outcome for publication under the lock.
+    void conclude(const std::shared_ptr<Job>& j, int outcome) {
+        j->t_done = now_ns();
+        if (j->x) X.release(*j);
+        j->inflight = false;
+        j->outcome = outcome;
+        done.push_back(j);
     }
-    std::vector<int> rcs(g.size(), ASEP_OK);
-    if (!S->X->queue(g, t_end, n, &rcs)) return false;
-    for (size_t i = 0; i < g.size(); ++i) {
-        if (rcs[i] == ASEP_OK)
-            mark_queued(S, *g[i], t0[i], t_end[i], n[i]);
-        else
-            failed->push_back({g[i], rcs[i]});
+
+    // The job's next quantum: end time and number of measurements in it.
+    void next_quantum(const Job& j, uint64_t* t_end_out, uint32_t* n_out) {
+        const uint64_t t = X.time(j);
+        const uint64_t q = std::min<uint64_t>(std::max<uint64_t>(S->cfg.quantum_mcs, 1),
+                                              std::max<uint64_t>(X.max_quantum_mcs(j), 1));
+        uint64_t t_end = (j.t_max - t > q) ? t + q : j.t_max;
+        const uint32_t cap = X.record_capacity(j);
+        uint32_t n = 0;
+        while (j.next_time + n < j.times.size() && j.times[j.next_time + n] <= t_end && n < cap)
+            ++n;
+        if (n == cap && j.next_time + n < j.times.size() && j.times[j.next_time + n] <= t_end)
+            t_end = j.times[j.next_time + n - 1];
+        *t_end_out = t_end;
+        *n_out = n;
     }
-    return true;
-}
 
-bool finished(asep_server* S, const Job& j) {
-    return S->X->time(j) >= j.t_max && j.next_time >= j.times.size();
-}
+    void mark_queued(Job& j, uint64_t t0, uint64_t t_end, uint32_t n, bool shared) {
+        if (!j.t_start) j.t_start = now_ns();
+        j.updates += (t_end - t0) * X.attempts_per_mcs(j);
+        j.staged_first = j.next_time;
+        j.staged_n = n;
+        j.next_time += n;
+        j.inflight = true;
+        j.quanta += 1;
+        if (shared) j.packed_quanta += 1;
+    }
 
-void worker_main(asep_server* S) {
-    Executor& X = *S->X;
-    const int rc0 = X.init();
-    std::unique_lock<std::mutex> lk(S->mu);
-    S->init_rc = rc0;
-    S->ready = true;
-    S->cv_done.notify_all();
-    while (!S->stop && S->init_rc == ASEP_OK) {
-        bool progressed = false;
-        // admission in arrival order while slots and memory allow
-        while (!S->queue.empty() && S->active.size() < S->cfg.max_active) {
-            auto j = S->queue.front();
-            S->queue.pop_front();
-            if (j->cancel) {
-                finish(S, *j, ASEP_E_CANCELLED);
-                progressed = true;
+    // Queue one quantum of each job of the group (one launch if several);
+    // false if the executor cannot take a shared launch now.
+    bool queue_group(const std::vector<Job*>& g, std::vector<std::pair<Job*, int>>* failed) {
+        std::vector<uint64_t> t_end(g.size()), t0(g.size());
+        std::vector<uint32_t> n(g.size());
+        for (size_t i = 0; i < g.size(); ++i) {
+            next_quantum(*g[i], &t_end[i], &n[i]);
+            t0[i] = X.time(*g[i]);
+        }
+        std::vector<int> rcs(g.size(), ASEP_OK);
+        std::vector<char> shared(g.size(), 0);
+        if (!X.queue(g, t_end, n, &rcs, &shared)) return false;
+        for (size_t i = 0; i < g.size(); ++i) {
+            if (rcs[i] == ASEP_OK)
+                mark_queued(*g[i], t0[i], t_end[i], n[i], shared[i] != 0);
+            else
+                failed->push_back({g[i], rcs[i]});
+        }
+        return true;
+    }
+
+    bool finished(const Job& j) { return X.time(j) >= j.t_max && j.next_time >= j.times.size(); }
+
+    // Admission of the candidates taken from the queue, in arrival order;
+    // those that find no room now go back (returned in order).
+    std::vector<std::shared_ptr<Job>> admit(std::vector<std::shared_ptr<Job>>& cand,
+                                            bool* progressed) {
+        std::vector<std::shared_ptr<Job>> back;
+        for (auto& j : cand) {
+            if (!back.empty()) {  // an earlier arrival is waiting for room
+                back.push_back(j);
                 continue;
             }
-            int rc = X.admit(*j);
+            if (j->cancel.load()) {
+                conclude(j, ASEP_E_CANCELLED);
+                *progressed = true;
+                continue;
+            }
+            const int rc = X.admit(*j);
             if (rc == ASEP_E_NOMEM) {
-                if (S->active.empty()) {
-                    finish(S, *j, ASEP_E_NOMEM);  // can never fit
-                    progressed = true;
+                if (active.empty()) {  // nothing resident: it can never fit
+                    conclude(j, ASEP_E_NOMEM);
+                    *progressed = true;
                     continue;
                 }
-                S->queue.push_front(j);  // back-pressure: wait for room
-                break;
+                back.push_back(j);  // back-pressure: wait for room
+                continue;
             }
             if (rc) {
-                finish(S, *j, rc);
-                progressed = true;
+                conclude(j, rc);
+                *progressed = true;
                 continue;
             }
             j->rough.assign(j->times.size() * (size_t)j->params.samples, asep_rough{});
             j->t_admit = now_ns();
             j->inflight = true;  // the initialisation is the job's first work
-            S->active.push_back(j);
-            progressed = true;
+            active.push_back(j);
+            *progressed = true;
         }
-        // progress: every request whose quantum is done gets its next one
+        return back;
+    }
+
+    // Every resident job whose quantum is done gets its next one; jobs that
+    // can share a launch go together.
+    void advance(bool* progressed) {
         std::vector<std::shared_ptr<Job>> still;
         std::vector<Job*> ready;
         std::vector<std::pair<Job*, int>> failed;
-        for (auto& jp : S->active) {
+        for (auto& jp : active) {
             Job& j = *jp;
             int rc = ASEP_OK;
             if (j.inflight) {
@@ -177,22 +190,21 @@ void worker_main(asep_server* S) {
                     j.staged_n = 0;
                     j.inflight = false;
                 }
-                progressed = true;
+                *progressed = true;
             }
-            if (rc == ASEP_OK && j.cancel) rc = ASEP_E_CANCELLED;
-            if (rc == ASEP_OK && finished(S, j)) {
-                finish(S, j, ASEP_OK);
+            if (rc == ASEP_OK && j.cancel.load()) rc = ASEP_E_CANCELLED;
+            if (rc == ASEP_OK && finished(j)) {
+                conclude(jp, ASEP_OK);
                 continue;
             }
             if (rc) {
-                X.sync_all();
-                finish(S, j, rc);
+                if (j.inflight) X.wait(j);  // a failed query: let its work drain
+                conclude(jp, rc);
                 continue;
             }
             ready.push_back(&j);
             still.push_back(jp);
         }
-        // ready jobs that may share a launch go together, the rest alone
         std::map<uint64_t, std::vector<Job*>> groups;
         std::vector<Job*> single;
         for (Job* j : ready) {
@@ -204,46 +216,96 @@ void worker_main(asep_server* S) {
         }
         for (auto& kv : groups) {
             auto& g = kv.second;
-            if (g.size() >= 2 && queue_group(S, g, &failed)) {
-                progressed = true;
+            if (g.size() >= 2 && queue_group(g, &failed)) {
+                *progressed = true;
                 continue;
             }
             for (Job* j : g) single.push_back(j);
         }
         for (Job* j : single) {
-            queue_group(S, {j}, &failed);
-            progressed = true;
+            queue_group({j}, &failed);
+            *progressed = true;
         }
         if (!failed.empty()) {
-            X.sync_all();
             std::vector<std::shared_ptr<Job>> keep;
             for (auto& jp : still) {
                 auto it = std::find_if(failed.begin(), failed.end(),
                                        [&](const std::pair<Job*, int>& f) { return f.first == jp.get(); });
-                if (it == failed.end())
+                if (it == failed.end()) {
                     keep.push_back(jp);
-                else
-                    finish(S, *jp, it->second);
+                } else {
+                    X.wait(*jp);  // whatever part of the quantum was queued
+                    conclude(jp, it->second);
+                }
             }
             still.swap(keep);
         }
-        S->active.swap(still);
-        if (progressed) S->cv_done.notify_all();
-        if (S->active.empty() && S->queue.empty()) {
-            S->cv_work.wait_for(lk, std::chrono::milliseconds(20));
-        } else if (!progressed) {
-            lk.unlock();
-            std::this_thread::sleep_for(std::chrono::microseconds(50));
-            lk.lock();
+        active.swap(still);
+    }
+
+    // Under the lock: outcomes become visible to the clients.
+    void publish() {
+        for (auto& j : done) j->status = j->outcome;
+        done.clear();
+    }
+};
+
+void worker_main(asep_server* S) {
+    Worker W{S, *S->X, {}, {}};
+    const int rc0 = W.X.init();
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->init_rc = rc0;
+        S->ready = true;
+    }
+    S->cv_done.notify_all();
+    if (rc0 == ASEP_OK) {
+        for (;;) {
+            // take the arrivals that may be admitted (under the lock)
+            std::vector<std::shared_ptr<Job>> cand;
+            {
+                std::lock_guard<std::mutex> lk(S->mu);
+                if (S->stop) break;
+                while (!S->queue.empty() && W.active.size() + cand.size() < S->cfg.max_active) {
+                    cand.push_back(S->queue.front());
+                    S->queue.pop_front();
+                }
+            }
+            // device work without the lock
+            bool progressed = false;
+            std::vector<std::shared_ptr<Job>> back = W.admit(cand, &progressed);
+            W.advance(&progressed);
+            // publish (under the lock), then wait for work or poll again
+            std::unique_lock<std::mutex> lk(S->mu);
+            for (auto it = back.rbegin(); it != back.rend(); ++it) S->queue.push_front(*it);
+            const bool any_done = !W.done.empty();
+            W.publish();
+            if (progressed || any_done) S->cv_done.notify_all();
+            if (S->stop) break;
+            if (W.active.empty() && S->queue.empty()) {
+                S->cv_work.wait_for(lk, std::chrono::milliseconds(20));
+            } else if (!progressed) {
+                lk.unlock();
+                std::this_thread::sleep_for(std::chrono::microseconds(50));
+            }
         }
     }
     // shutdown: wait for work in flight, release everything
-    X.sync_all();
-    for (auto& j : S->active) finish(S, *j, ASEP_E_CANCELLED);
-    S->active.clear();
-    for (auto& j : S->queue) finish(S, *j, S->init_rc ? S->init_rc : ASEP_E_CANCELLED);
-    S->queue.clear();
-    X.shutdown();
+    W.X.sync_all();
+    for (auto& j : W.active) W.conclude(j, ASEP_E_CANCELLED);
+    W.active.clear();
+    std::vector<std::shared_ptr<Job>> left;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        left.assign(S->queue.begin(), S->queue.end());
+        S->queue.clear();
+    }
+    for (auto& j : left) W.conclude(j, S->init_rc ? S->init_rc : ASEP_E_CANCELLED);
+    W.X.shutdown();
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        W.publish();
+    }
     S->cv_done.notify_all();
 }
 
@@ -257,6 +319,10 @@ int fill_result(const Job& j, asep_result* out) {
     out->t_start_ns = j.t_start;
     out->t_done_ns = j.t_done;
     out->site_updates = j.updates;
+    out->params = j.resolved;
+    out->plan = j.plan;
+    out->quanta = j.quanta;
+    out->packed_quanta = j.packed_quanta;
     if (j.status == ASEP_OK && !j.times.empty()) {
         out->times = (uint64_t*)std::malloc(8 * j.times.size());
         out->rough = (asep_rough*)std::malloc(sizeof(asep_rough) * j.rough.size());
@@ -295,8 +361,6 @@ int server_create_with(const asep_server_cfg* cfg, std::unique_ptr<Executor> x,
     if (!S->cfg.max_queue) S->cfg.max_queue = 1024;
     if (!S->cfg.max_active) S->cfg.max_active = 64;
     if (!S->cfg.quantum_mcs) S->cfg.quantum_mcs = 1000;
-    // a quantum is one launch of at most 2^30 sub-sweeps (4 per MCS at most)
-    if (S->cfg.quantum_mcs > (1ull << 28)) S->cfg.quantum_mcs = 1ull << 28;
     if (!S->cfg.hbm_budget_bytes) S->cfg.hbm_budget_bytes = (uint64_t)8 << 30;
     S->X = std::move(x);
     try {
@@ -316,6 +380,10 @@ using asep::serve::now_ns;
 
 extern "C" int asep_server_create(const asep_server_cfg* cfg, asep_server** out) {
     if (!cfg || !out || cfg->abi_version != ASEP_ABI_VERSION) return ASEP_E_INVAL;
+    if (cfg->tuning_path) {
+        const int rc = asep_tuning_load(cfg->tuning_path);
+        if (rc) return rc;
+    }
     asep_server_cfg c = *cfg;
     if (!c.max_active) c.max_active = 64;
     if (!c.hbm_budget_bytes) c.hbm_budget_bytes = (uint64_t)8 << 30;

@@ -6,6 +6,11 @@
 // request's simulation; several small whole-ring requests with the same
 // kernel shape share one packed launch on a free pool stream (their
 // descriptors in device memory).
+//
+// Nothing that waits on the device runs while requests come and go: pinned
+// record staging and events are taken from pools that grow on demand and
+// are freed only at shutdown (freeing pinned host memory waits for the whole
+// device), and a finished request's arena range is simply marked free.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -91,8 +96,44 @@ struct Resident {
     void* state = nullptr;
     void* aux = nullptr;
     hipStream_t stream = nullptr;
+    hipStream_t last = nullptr;  // stream of the request's latest queued work
     hipEvent_t done_ev = nullptr;
     Record* pinned_rec = nullptr;
+    size_t pinned_bytes = 0;
+};
+
+// Pinned host buffers by capacity (powers of two), reused and freed only at
+// shutdown.
+class PinnedPool {
+   public:
+    Record* take(size_t bytes, size_t* cap) {
+        size_t c = 4096;
+        while (c < bytes) c <<= 1;
+        auto it = free_.lower_bound(c);
+        if (it != free_.end() && it->first == c) {
+            Record* r = it->second;
+            free_.erase(it);
+            *cap = c;
+            return r;
+        }
+        void* p = nullptr;
+        if (hipHostMalloc(&p, c) != hipSuccess) return nullptr;
+        all_.push_back(p);
+        *cap = c;
+        return (Record*)p;
+    }
+    void give(Record* r, size_t cap) {
+        if (r) free_.emplace(cap, r);
+    }
+    void release() {
+        for (void* p : all_) (void)hipHostFree(p);
+        all_.clear();
+        free_.clear();
+    }
+
+   private:
+    std::multimap<size_t, Record*> free_;
+    std::vector<void*> all_;
 };
 
 constexpr uint32_t kStreams = 8;
@@ -120,6 +161,9 @@ class DeviceExecutor final : public Executor {
     void shutdown() override {
         sync_all();
         arena_.release();
+        pinned_.release();
+        for (hipEvent_t e : events_) (void)hipEventDestroy(e);
+        events_.clear();
         for (uint32_t i = 0; i < kStreams; ++i) {
             if (pack_host_[i]) (void)hipHostFree(pack_host_[i]);
             if (pack_dev_[i]) (void)hipFree(pack_dev_[i]);
@@ -133,7 +177,7 @@ class DeviceExecutor final : public Executor {
     }
 
     int footprint(const asep_params& p, size_t* state_bytes, size_t* aux_bytes) override {
-        return asep_buffer_sizes(&p, state_bytes, aux_bytes);
+        return sim_buffer_sizes_on(&p, cfg_.device, state_bytes, aux_bytes);
     }
 
     int admit(Job& j) override {
@@ -148,18 +192,17 @@ class DeviceExecutor final : public Executor {
         }
         j.x = r;
         r->stream = streams_[next_stream_++ % kStreams];
-        int rc = asep_create_ext(&j.params, r->state, j.state_bytes, r->aux, j.aux_bytes,
-                                 r->stream, &r->sim);
-        if (rc == ASEP_OK &&
-            hipEventCreateWithFlags(&r->done_ev, hipEventDisableTiming) != hipSuccess)
-            rc = ASEP_E_DEVICE;
-        if (rc == ASEP_OK &&
-            hipHostMalloc((void**)&r->pinned_rec,
-                          sizeof(Record) * sim_record_capacity(r->sim) * j.params.samples) !=
-                hipSuccess) {
-            r->pinned_rec = nullptr;
-            rc = ASEP_E_DEVICE;
+        r->last = r->stream;
+        int rc = ASEP_OK;
+        r->pinned_rec = pinned_.take(sim_host_rec_bytes(j.params), &r->pinned_bytes);
+        if (!r->pinned_rec) rc = ASEP_E_DEVICE;
+        if (rc == ASEP_OK) {
+            r->done_ev = take_event();
+            if (!r->done_ev) rc = ASEP_E_DEVICE;
         }
+        if (rc == ASEP_OK)
+            rc = sim_create_borrowed(&j.params, r->state, j.state_bytes, r->aux, j.aux_bytes,
+                                     r->stream, r->pinned_rec, &r->sim);
         // the initialisation kernels are the job's first work in flight
         if (rc == ASEP_OK && hipEventRecord(r->done_ev, r->stream) != hipSuccess)
             rc = ASEP_E_DEVICE;
@@ -168,23 +211,32 @@ class DeviceExecutor final : public Executor {
             release(j);
             return rc == ASEP_E_NOMEM ? ASEP_E_DEVICE : rc;
         }
+        sim_describe(r->sim, &j.resolved, &j.plan);
         return ASEP_OK;
     }
 
     void release(Job& j) override {
         auto* r = res(j);
         if (!r) return;
-        if (r->sim) asep_destroy(r->sim);  // the job has no work in flight
+        // the job has no work in flight; its simulation borrows stream,
+        // buffers and staging, so destroying it waits for nothing
+        if (r->sim) asep_destroy(r->sim);
         arena_.free(r->state);
         arena_.free(r->aux);
-        if (r->done_ev) (void)hipEventDestroy(r->done_ev);
-        if (r->pinned_rec) (void)hipHostFree(r->pinned_rec);
+        if (r->done_ev) events_free_.push_back(r->done_ev);
+        pinned_.give(r->pinned_rec, r->pinned_bytes);
         delete r;
         j.x = nullptr;
     }
 
+    void wait(Job& j) override {
+        Resident* r = res(j);
+        if (r && r->last) (void)hipStreamSynchronize(r->last);
+    }
+
     uint64_t time(const Job& j) override { return asep_time(res(j)->sim); }
     uint32_t record_capacity(const Job& j) override { return sim_record_capacity(res(j)->sim); }
+    uint64_t max_quantum_mcs(const Job& j) override { return sim_max_quantum_mcs(res(j)->sim); }
     uint64_t attempts_per_mcs(const Job& j) override { return sim_attempts_per_mcs(res(j)->sim); }
 
     int query(Job& j) override {
@@ -211,18 +263,14 @@ class DeviceExecutor final : public Executor {
     }
 
     bool queue(const std::vector<Job*>& g, const std::vector<uint64_t>& t_end,
-               const std::vector<uint32_t>& n, std::vector<int>* rcs) override {
+               const std::vector<uint32_t>& n, std::vector<int>* rcs,
+               std::vector<char>* shared) override {
         if (g.size() == 1) {
-            Job& j = *g[0];
-            Resident* r = res(j);
-            int rc = sim_run_async(r->sim, j.times.data() + j.next_time, n[0], t_end[0],
-                                   r->pinned_rec);
-            if (rc == ASEP_OK && hipEventRecord(r->done_ev, r->stream) != hipSuccess)
-                rc = ASEP_E_DEVICE;
-            (*rcs)[0] = rc;
+            (*rcs)[0] = queue_alone(*g[0], t_end[0], n[0]);
+            (*shared)[0] = 0;
             return true;
         }
-        return queue_packed(g, t_end, n, rcs);
+        return queue_packed(g, t_end, n, rcs, shared);
     }
 
     void sync_all() override {
@@ -233,9 +281,33 @@ class DeviceExecutor final : public Executor {
    private:
     static Resident* res(const Job& j) { return static_cast<Resident*>(j.x); }
 
+    hipEvent_t take_event() {
+        if (!events_free_.empty()) {
+            hipEvent_t e = events_free_.back();
+            events_free_.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+        events_.push_back(e);
+        return e;
+    }
+
+    // One quantum of one job on its own stream (cut into as many launches
+    // as the run needs).
+    int queue_alone(Job& j, uint64_t t_end, uint32_t n) {
+        Resident* r = res(j);
+        r->last = r->stream;
+        int rc = sim_run_async(r->sim, j.times.data() + j.next_time, n, t_end, r->pinned_rec);
+        if (rc == ASEP_OK && hipEventRecord(r->done_ev, r->stream) != hipSuccess)
+            rc = ASEP_E_DEVICE;
+        return rc;
+    }
+
     // Several jobs of one kernel shape as one launch on a free pool stream.
     bool queue_packed(const std::vector<Job*>& g, const std::vector<uint64_t>& t_end,
-                      const std::vector<uint32_t>& n, std::vector<int>* rcs) {
+                      const std::vector<uint32_t>& n, std::vector<int>* rcs,
+                      std::vector<char>* shared) {
         uint32_t slot = kStreams;
         for (uint32_t k = 0; k < kStreams; ++k) {
             if (!pack_used_[k] || hipEventQuery(pack_ev_[k]) == hipSuccess) {
@@ -263,11 +335,13 @@ class DeviceExecutor final : public Executor {
             lds = std::max(lds, ji.lds);
         }
         if (!ok) {
-            // nothing was queued: the jobs whose preparation failed fail,
-            // the others go on with their next quantum
-            for (size_t i = 0; i < g.size(); ++i)
-                if (!(*rcs)[i]) (*rcs)[i] = ASEP_E_PENDING;
-            return queue_fallback(g, t_end, n, rcs);
+            // nothing was queued: every job of the group runs its quantum
+            // alone (a run too long for one launch is cut there)
+            for (size_t i = 0; i < g.size(); ++i) {
+                (*rcs)[i] = queue_alone(*g[i], t_end[i], n[i]);
+                (*shared)[i] = 0;
+            }
+            return true;
         }
         const uint32_t nd = (uint32_t)g.size();
         hipError_t e = hipMemcpyAsync(pack_dev_[slot], hd, sizeof(SimDesc) * nd,
@@ -281,26 +355,15 @@ class DeviceExecutor final : public Executor {
         for (size_t i = 0; i < g.size(); ++i) {
             Job& j = *g[i];
             Resident* r = res(j);
+            r->last = st;
             int rc = (e == hipSuccess) ? ASEP_OK : device_error(e, "packed launch");
             if (rc == ASEP_OK) rc = sim_pack_commit(r->sim, t_end[i], n[i], r->pinned_rec, st);
             if (rc == ASEP_OK && hipEventRecord(r->done_ev, st) != hipSuccess) rc = ASEP_E_DEVICE;
             (*rcs)[i] = rc;
+            (*shared)[i] = 1;
         }
         (void)hipEventRecord(pack_ev_[slot], st);
         pack_used_[slot] = true;
-        return true;
-    }
-
-    // After a failed packed preparation: jobs marked pending are queued
-    // alone; the failed ones keep their error.
-    bool queue_fallback(const std::vector<Job*>& g, const std::vector<uint64_t>& t_end,
-                        const std::vector<uint32_t>& n, std::vector<int>* rcs) {
-        for (size_t i = 0; i < g.size(); ++i) {
-            if ((*rcs)[i] != ASEP_E_PENDING) continue;
-            std::vector<int> one(1, ASEP_OK);
-            queue({g[i]}, {t_end[i]}, {n[i]}, &one);
-            (*rcs)[i] = one[0];
-        }
         return true;
     }
 
@@ -312,6 +375,9 @@ class DeviceExecutor final : public Executor {
     SimDesc* pack_dev_[kStreams] = {};
     hipEvent_t pack_ev_[kStreams] = {};
     bool pack_used_[kStreams] = {};
+    PinnedPool pinned_;
+    std::vector<hipEvent_t> events_;       // every event created
+    std::vector<hipEvent_t> events_free_;  // of those, the ones not in use
 };
 
 }  // namespace

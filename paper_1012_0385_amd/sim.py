@@ -18,7 +18,7 @@ def make_params(L: int, samples: int = 1, *, model: int = B.ASEP_MODEL_RING,
                 q: float = 0.0, slow_frac: float = 0.0, slow_factor: float = 1.0,
                 samples_per_disorder: int = 1, lane_rate: float = 0.0, turn_frac: float = 0.0,
                 seed: int = 1, stream: int = 0, cell_log2: int = 0, subsweeps: int = 0,
-                rbits: int = -1, sample_offset: int = 0, windows: int = 0,
+                rbits: int = 0, sample_offset: int = 0, windows: int = 0,
                 window_sweeps: int = 0, rings_per_wg: int = 0,
                 schedule: int = B.ASEP_SCHED_SHIFTED) -> B.asep_params:
     P = B.asep_params()
@@ -116,6 +116,12 @@ class Simulation:
     @property
     def handle(self):
         return self._h
+
+    def plan(self) -> dict:
+        """The launch plan (asep_get_plan) as a dict."""
+        pl = B.asep_plan()
+        B.check(B.load().asep_get_plan(self._h, ctypes.byref(pl)), "asep_get_plan")
+        return {n: int(getattr(pl, n)) for n, _ in B.asep_plan._fields_ if n != "reserved"}
 
     @property
     def time(self) -> int:
@@ -240,11 +246,29 @@ def ensemble_w2(rough_list, L: int) -> float:
     return out.value
 
 
+def resolve(params: B.asep_params):
+    """asep_resolve: (resolved parameters, plan dict) without creating anything."""
+    out = B.asep_params()
+    pl = B.asep_plan()
+    B.check(B.load().asep_resolve(ctypes.byref(params), ctypes.byref(out), ctypes.byref(pl)),
+            "asep_resolve")
+    return out, {n: int(getattr(pl, n)) for n, _ in B.asep_plan._fields_ if n != "reserved"}
+
+
+def load_tuning(path) -> None:
+    """asep_tuning_load: the process-wide tuning table (None clears it)."""
+    B.check(B.load().asep_tuning_load(path.encode() if path else None), "asep_tuning_load")
+
+
+def _params_dict(P) -> dict:
+    return {n: getattr(P, n) for n, _ in B.asep_params._fields_}
+
+
 class Server:
     """The request loop (asep_server_*): submit ensemble runs, collect results."""
 
     def __init__(self, *, device: int = 0, hbm_budget_bytes: int = 8 << 30, max_queue: int = 1024,
-                 max_active: int = 64, quantum_mcs: int = 1000):
+                 max_active: int = 64, quantum_mcs: int = 1000, tuning_path=None):
         cfg = B.asep_server_cfg()
         cfg.abi_version = B.ASEP_ABI_VERSION
         cfg.device = device
@@ -252,6 +276,7 @@ class Server:
         cfg.max_queue = max_queue
         cfg.max_active = max_active
         cfg.quantum_mcs = quantum_mcs
+        cfg.tuning_path = tuning_path.encode() if tuning_path else None
         self._h = ctypes.c_void_p()
         B.check(B.load().asep_server_create(ctypes.byref(cfg), ctypes.byref(self._h)),
                 "asep_server_create")
@@ -274,6 +299,10 @@ class Server:
                "n_times": int(res.n_times), "arrive_ns": int(res.t_arrive_ns),
                "admit_ns": int(res.t_admit_ns), "start_ns": int(res.t_start_ns),
                "done_ns": int(res.t_done_ns), "site_updates": int(res.site_updates),
+               "params": _params_dict(res.params),
+               "plan": {n: int(getattr(res.plan, n)) for n, _ in B.asep_plan._fields_
+                        if n != "reserved"},
+               "quanta": int(res.quanta), "packed_quanta": int(res.packed_quanta),
                "rough": []}
         if res.status == B.ASEP_OK and res.n_times:
             n, R = res.n_times, res.samples

@@ -49,7 +49,7 @@ orc_params to_orc(const asep_params& p) {
     o.stream = p.stream;
     o.cell_log2 = p.cell_log2 ? (uint32_t)p.cell_log2 : 6;
     o.subsweeps = p.subsweeps ? (uint32_t)p.subsweeps : 4;
-    o.rbits = p.rbits;
+    o.rbits = p.rbits > 0 ? p.rbits : -1;  // the library's 0 means automatic
     o.schedule = p.schedule == ASEP_SCHED_SUBLATTICE ? ORC_SCHED_SUBLATTICE : ORC_SCHED_SHIFTED;
     return o;
 }
@@ -83,12 +83,15 @@ struct FakeJob {
 
 class FakeExecutor final : public Executor {
    public:
-    FakeExecutor(size_t budget, uint32_t cap, int max_polls, uint32_t refuse_every)
-        : budget_(budget), cap_(cap), max_polls_(max_polls), refuse_every_(refuse_every) {}
+    FakeExecutor(size_t budget, uint32_t cap, int max_polls, uint32_t refuse_every,
+                 uint64_t max_q = ~0ull)
+        : budget_(budget), cap_(cap), max_polls_(max_polls), refuse_every_(refuse_every),
+          max_q_(max_q) {}
 
     std::vector<uint64_t> admitted;  // tickets in admission order (read after the run)
     std::atomic<uint64_t> n_admitted{0};
     std::atomic<uint64_t> shared_launches{0};
+    std::atomic<uint64_t> longest_quantum{0};
 
     int init() override { return ASEP_OK; }
     void shutdown() override {}
@@ -121,6 +124,10 @@ class FakeExecutor final : public Executor {
         f->polls = next_polls();
         used_ += need;
         j.x = f;
+        j.resolved = j.params;
+        j.resolved.cell_log2 = (int32_t)f->P.cell_log2;
+        j.resolved.subsweeps = (int32_t)f->P.subsweeps;
+        j.plan = asep_plan{};
         admitted.push_back(j.ticket);
         n_admitted++;
         return ASEP_OK;
@@ -133,8 +140,10 @@ class FakeExecutor final : public Executor {
         j.x = nullptr;
     }
 
+    void wait(Job&) override {}
     uint64_t time(const Job& j) override { return fj(j)->t; }
     uint32_t record_capacity(const Job&) override { return cap_; }
+    uint64_t max_quantum_mcs(const Job&) override { return max_q_; }
     uint64_t attempts_per_mcs(const Job& j) override {
         return (uint64_t)j.params.samples * j.params.L *
                (j.params.model == ASEP_MODEL_TWO_LANE ? 4 : 1);
@@ -182,14 +191,18 @@ class FakeExecutor final : public Executor {
     }
 
     bool queue(const std::vector<Job*>& g, const std::vector<uint64_t>& t_end,
-               const std::vector<uint32_t>& n, std::vector<int>* rcs) override {
+               const std::vector<uint32_t>& n, std::vector<int>* rcs,
+               std::vector<char>* shared) override {
         if (g.size() > 1) {
             if (refuse_every_ && (++tries_ % refuse_every_) == 0) return false;
             shared_launches++;
         }
         for (size_t i = 0; i < g.size(); ++i) {
             auto* f = fj(*g[i]);
-            if (t_end[i] < f->t || f->q_n || n[i] > cap_) {
+            (*shared)[i] = g.size() > 1;
+            const uint64_t len = t_end[i] >= f->t ? t_end[i] - f->t : 0;
+            if (len > longest_quantum) longest_quantum = len;
+            if (t_end[i] < f->t || f->q_n || n[i] > cap_ || len > max_q_) {
                 (*rcs)[i] = ASEP_E_INVAL;
                 continue;
             }
@@ -216,6 +229,7 @@ class FakeExecutor final : public Executor {
     uint32_t cap_;
     int max_polls_;
     uint32_t refuse_every_, tries_ = 0;
+    uint64_t max_q_;
     uint64_t lcg_ = 12345;
 };
 
@@ -327,7 +341,7 @@ Req random_request(int i) {
 
 asep_server* make_server(FakeExecutor** fx, size_t budget, uint32_t cap, int polls,
                          uint32_t refuse, uint32_t max_active, uint32_t max_queue,
-                         uint64_t quantum) {
+                         uint64_t quantum, uint64_t max_q = ~0ull) {
     asep_server_cfg cfg;
     memset(&cfg, 0, sizeof cfg);
     cfg.abi_version = ASEP_ABI_VERSION;
@@ -335,7 +349,7 @@ asep_server* make_server(FakeExecutor** fx, size_t budget, uint32_t cap, int pol
     cfg.max_queue = max_queue;
     cfg.quantum_mcs = quantum;
     cfg.hbm_budget_bytes = budget;
-    auto x = std::unique_ptr<Executor>(new FakeExecutor(budget, cap, polls, refuse));
+    auto x = std::unique_ptr<Executor>(new FakeExecutor(budget, cap, polls, refuse, max_q));
     *fx = static_cast<FakeExecutor*>(x.get());
     asep_server* S = nullptr;
     if (asep::serve::server_create_with(&cfg, std::move(x), &S) != ASEP_OK) return nullptr;
@@ -369,16 +383,22 @@ void scenario_mix() {
         tickets.push_back(submit(S, reqs.back(), &rc));
         check(rc == ASEP_OK, "mix.submit", i, rc);
     }
+    uint64_t packed = 0;
     for (size_t i = 0; i < reqs.size(); ++i) {
         asep_result res;
         int rc = asep_wait(S, tickets[i], kWait, &res);
         check(rc == ASEP_OK && equals_alone(reqs[i], res), "mix.equals_alone", (long)i, rc);
+        check(res.quanta >= 1 && res.packed_quanta <= res.quanta, "mix.quanta", (long)res.quanta,
+              (long)res.packed_quanta);
+        packed += res.packed_quanta;
         check(res.t_arrive_ns <= res.t_admit_ns && res.t_admit_ns <= res.t_start_ns &&
                   res.t_start_ns <= res.t_done_ns,
               "mix.timestamps", (long)i);
         asep_result_free(&res);
     }
-    check(fx->shared_launches > 0, "mix.shared_launches", (long)fx->shared_launches);
+    check((fx->shared_launches > 0) == (packed > 0), "mix.shared_counted",
+          (long)fx->shared_launches, (long)packed);
+
     std::vector<uint64_t> order = fx->admitted;
     check(std::is_sorted(order.begin(), order.end()), "mix.admission_in_arrival_order");
     asep_server_destroy(S);
@@ -489,20 +509,136 @@ void scenario_limits() {
     asep_server_destroy(S);
 }
 
+// Requests of one kernel shape whose quanta end together share launches,
+// and each still equals its run alone.
+void scenario_packing() {
+    FakeExecutor* fx;
+    asep_server* S = make_server(&fx, 1 << 20, 64, 0, 0, 8, 64, 4);
+    std::vector<Req> reqs;
+    std::vector<uint64_t> tickets;
+    for (int i = 0; i < 8; ++i) {
+        Req r = random_request(0);  // the first model: shifted cells of 16
+        r.p.L = 256;
+        r.p.seed = 60 + i;
+        r.t_max = 24;
+        r.times = {0, 5, 17, 24};
+        reqs.push_back(r);
+        int rc;
+        tickets.push_back(submit(S, r, &rc));
+    }
+    uint64_t packed = 0;
+    for (size_t i = 0; i < reqs.size(); ++i) {
+        asep_result res;
+        int rc = asep_wait(S, tickets[i], kWait, &res);
+        check(rc == ASEP_OK && equals_alone(reqs[i], res), "packing.equals_alone", (long)i);
+        packed += res.packed_quanta;
+        asep_result_free(&res);
+    }
+    check(fx->shared_launches > 0 && packed > 0, "packing.shared_launches",
+          (long)fx->shared_launches, (long)packed);
+    asep_server_destroy(S);
+}
+
+// A quantum configured far longer than the executor allows (one launch of a
+// whole ring has a sub-sweep cap): every quantum the core queues is cut to
+// the executor's limit, and every request still equals its run alone.
+void scenario_quantum_clamp() {
+    FakeExecutor* fx;
+    asep_server* S = make_server(&fx, 1 << 20, 64, 1, 2, 8, 64, 1ull << 40, 3);
+    std::vector<Req> reqs;
+    std::vector<uint64_t> tickets;
+    for (int i = 0; i < 8; ++i) {
+        reqs.push_back(random_request(i));
+        int rc;
+        tickets.push_back(submit(S, reqs.back(), &rc));
+    }
+    for (size_t i = 0; i < reqs.size(); ++i) {
+        asep_result res;
+        int rc = asep_wait(S, tickets[i], kWait, &res);
+        check(rc == ASEP_OK && equals_alone(reqs[i], res), "quantum.equals_alone", (long)i,
+              res.status);
+        check(res.quanta >= (reqs[i].t_max + 2) / 3, "quantum.count", (long)res.quanta);
+        check(res.params.cell_log2 == (reqs[i].p.cell_log2 ? reqs[i].p.cell_log2 : 6) ||
+                  reqs[i].p.schedule == ASEP_SCHED_SUBLATTICE,
+              "quantum.schedule_echoed", (long)res.params.cell_log2);
+        asep_result_free(&res);
+    }
+    check(fx->longest_quantum <= 3, "quantum.clamped", (long)fx->longest_quantum);
+    asep_server_destroy(S);
+}
+
+// Several client threads submit, wait, poll and cancel at once; every
+// request that was not cancelled equals its run alone.
+void scenario_concurrent_clients() {
+    FakeExecutor* fx;
+    asep_server* S = make_server(&fx, 64 * 1024, 8, 2, 4, 6, 256, 5);
+    std::atomic<int> bad{0}, good{0};
+    std::vector<std::vector<Req>> drawn(4);
+    for (int c = 0; c < 4; ++c)
+        for (int i = 0; i < 6; ++i) drawn[c].push_back(random_request(10 * c + i));
+    std::vector<std::thread> th;
+    for (int c = 0; c < 4; ++c) {
+        th.emplace_back([&, c] {
+            std::vector<Req> reqs;
+            std::vector<uint64_t> tickets;
+            for (int i = 0; i < 6; ++i) {
+                const Req& r = drawn[c][i];
+                int rc = ASEP_E_BUSY;
+                uint64_t t = 0;
+                while (rc == ASEP_E_BUSY) t = submit(S, r, &rc);
+                if (rc != ASEP_OK) {
+                    ++bad;
+                    continue;
+                }
+                reqs.push_back(r);
+                tickets.push_back(t);
+                if (i == 3) asep_cancel(S, t);
+            }
+            for (size_t i = 0; i < reqs.size(); ++i) {
+                asep_result res;
+                int rc = ASEP_E_PENDING;
+                if (i % 2) {
+                    while ((rc = asep_poll(S, tickets[i], &res)) == ASEP_E_PENDING)
+                        std::this_thread::sleep_for(std::chrono::microseconds(200));
+                } else {
+                    rc = asep_wait(S, tickets[i], kWait, &res);
+                }
+                if (rc != ASEP_OK) {
+                    ++bad;
+                    continue;
+                }
+                if (res.status == ASEP_E_CANCELLED ? i == 3 : equals_alone(reqs[i], res))
+                    ++good;
+                else
+                    ++bad;
+                asep_result_free(&res);
+            }
+        });
+    }
+    for (auto& t : th) t.join();
+    check(bad == 0 && good == 24, "concurrent.all_requests", good.load(), bad.load());
+    asep_server_destroy(S);
+}
+
 }  // namespace
 
-// The device executor is not part of this program.
+// The device executor and the host library's tuning table are not part of
+// this program.
 namespace asep {
 namespace serve {
 std::unique_ptr<Executor> make_device_executor(const asep_server_cfg&) { return nullptr; }
 }  // namespace serve
 }  // namespace asep
+extern "C" int asep_tuning_load(const char*) { return ASEP_OK; }
 
 int main() {
     scenario_mix();
     scenario_backpressure();
     scenario_cancel();
     scenario_limits();
+    scenario_packing();
+    scenario_quantum_clamp();
+    scenario_concurrent_clients();
     printf("%s %d failures\n", failures ? "FAILED" : "PASSED", failures);
     return failures ? 1 : 0;
 }

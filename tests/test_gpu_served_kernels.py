@@ -1,0 +1,163 @@
+"""Oracle parity of the kernels the request loop reaches.
+
+A whole ring takes the fewest 64-site slots per lane that fit one workgroup:
+one slot up to 2^16 sites, two up to 2^17 (single lane), eight up to 2^18,
+sixteen up to 2^19; two lanes hold twice the state and take four slots at
+2^17 and eight at 2^18.  Each case below forces one such instantiation by its
+ring size, asserts the launch plan that ran (slots per lane, attempt loop,
+backward hops), and compares the library with the oracle bit for bit: with
+the measurements inside the launch (records at every time and the final
+words) and as a bare sweep (final words and hop counts).  Then requests
+drawn like the served mix run through the request loop at the benchmark's
+serving parameters (quantum 2000 MCS, 64 resident requests) and every
+request is compared with the oracle, not only with its own run alone.
+"""
+from concurrent.futures import ThreadPoolExecutor
+
+import pytest
+
+from parity_util import check_records, compare, oracle_params_from, sweep_and_compare_states
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+import paper_1012_0385_amd as A  # noqa: E402
+from paper_1012_0385_amd import binding as B  # noqa: E402
+from paper_1012_0385_amd import workloads as W  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def pool():
+    with ThreadPoolExecutor(8) as ex:
+        yield ex
+
+
+# single lane: (rates, attempt loop, backward hops)
+RING_CASES = [
+    (dict(p=1.0, q=0.0), B.ASEP_LOOP_F5B0, 0),                                  # KPZ
+    (dict(p=0.5, q=0.5, init=1, density=0.45), B.ASEP_LOOP_F4B1, 1),            # EW
+    (dict(p=0.75, q=0.25, init=1, density=0.4), B.ASEP_LOOP_F4B2, 1),
+    (dict(p=0.8, q=0.1, init=1), B.ASEP_LOOP_F1, 1),                            # 26 compared bits
+    (dict(p=1.0, q=0.0, slow_frac=0.1, slow_factor=0.5, samples_per_disorder=2),
+     B.ASEP_LOOP_F4B1, 0),                                                      # disorder, q = 0
+    (dict(p=1.0, q=1.0, slow_frac=0.2, slow_factor=0.5, init=1, density=0.5),
+     B.ASEP_LOOP_F4B1, 1),                                                      # disorder, q > 0
+    (dict(p=0.8, q=0.2, slow_frac=0.2, slow_factor=0.5, init=1), B.ASEP_LOOP_F1, 1),
+    (dict(p=0.75, q=0.25, slow_frac=0.3, slow_factor=0.5, init=1),
+     B.ASEP_LOOP_GENERIC, 1),                                                   # 3 bits: 3 per draw
+    (dict(p=0.9, q=0.3, cell_log2=5, subsweeps=2, init=1), B.ASEP_LOOP_GENERIC, 1),
+]
+
+# ring size -> slots per lane of a whole single-lane ring
+RING_SIZES = [(1 << 17, 2), (1 << 18, 8)]
+
+
+def _ids(cases):
+    return ["%s-%d" % ("_".join("%s%s" % kv for kv in c[0].items()), c[1]) for c in cases]
+
+
+@pytest.mark.parametrize("L,C", RING_SIZES, ids=["L2p17", "L2p18"])
+@pytest.mark.parametrize("rates,loop,bwd", RING_CASES, ids=_ids(RING_CASES))
+def test_whole_ring_loops_measured(orc, pool, L, C, rates, loop, bwd):
+    kw = dict(L=L, seed=3, stream=C, windows=1, **rates)
+    plan = dict(windows=1, slots_per_lane=C, attempt_loop=loop, backward_hops=bwd)
+    compare(orc, A, kw, [0, 1, 4, 9], 3, plan=plan, pool=pool)
+
+
+@pytest.mark.parametrize("L,C", RING_SIZES, ids=["L2p17", "L2p18"])
+@pytest.mark.parametrize("rates,loop,bwd", RING_CASES, ids=_ids(RING_CASES))
+def test_whole_ring_loops_bare_sweep(orc, L, C, rates, loop, bwd):
+    kw = dict(L=L, seed=5, stream=10 + C, windows=1, **rates)
+    plan = dict(windows=1, slots_per_lane=C, attempt_loop=loop, backward_hops=bwd)
+    sweep_and_compare_states(orc, A, kw, 7, 2, plan=plan)
+
+
+def test_sixteen_slots_disorder_both_directions(orc, pool):
+    # 2^19 sites: 16 slots per lane, disorder with backward hops (five
+    # outcome-index bits: pair, one compared bit, two marks)
+    kw = dict(L=1 << 19, p=1.0, q=1.0, slow_frac=0.2, slow_factor=0.5, init=1, seed=2,
+              stream=7, windows=1)
+    plan = dict(slots_per_lane=16, attempt_loop=B.ASEP_LOOP_F4B1, backward_hops=1)
+    compare(orc, A, kw, [0, 1, 3], 2, plan=plan, pool=pool)
+    sweep_and_compare_states(orc, A, kw, 3, 1, plan=plan)
+
+
+LANE_CASES = [
+    (dict(p=1.0, q=1.0, lane_rate=1.0, turn_frac=0.05), B.ASEP_LOOP_F4B0_LANES),
+    (dict(p=1.0, q=1.0, lane_rate=0.1, turn_frac=0.05), B.ASEP_LOOP_F1),    # 24 compared bits
+    (dict(p=0.5, q=0.5, lane_rate=0.5, turn_frac=0.2), B.ASEP_LOOP_GENERIC),  # 3 per draw
+]
+
+
+@pytest.mark.parametrize("L,C", [(1 << 17, 4), (1 << 18, 8)], ids=["L2p17", "L2p18"])
+@pytest.mark.parametrize("rates,loop", LANE_CASES, ids=_ids([(c[0], c[1]) for c in LANE_CASES]))
+def test_two_lane_whole_rings(orc, pool, L, C, rates, loop):
+    kw = dict(L=L, model=1, init=1, density=0.3, seed=4, stream=20 + C, windows=1, **rates)
+    plan = dict(windows=1, slots_per_lane=C, attempt_loop=loop)
+    compare(orc, A, kw, [0, 1, 3], 2, plan=plan, pool=pool)
+    sweep_and_compare_states(orc, A, kw, 2, 1, plan=plan)
+
+
+def _server_vs_oracle(orc, pool, reqs, **server_kw):
+    """Submit every request, then compare each (all samples, all times) with
+    the oracle run alone."""
+    srv = A.Server(**server_kw)
+    tickets = []
+    for r in reqs:
+        kw, samples, times, t_max = r
+        print("submit", kw, samples, "t_max", t_max, flush=True)
+        tickets.append(srv.submit(A.make_params(samples=samples, **kw), times, t_max))
+    results = [srv.wait(t, timeout_s=300) for t in tickets]
+    srv.close()
+    for (kw, samples, times, t_max), res in zip(reqs, results):
+        assert res["status"] == 0, (kw, res["status"])
+        # the resolved parameters of the same request created alone
+        sim = A.Simulation(A.make_params(samples=1, **kw), buffers="library")
+        OP = oracle_params_from(orc, sim.params)
+        sim.close()
+        refs = [pool.submit(orc.run, OP, int(kw.get("sample_offset", 0)) + i, times)
+                for i in range(samples)]
+        for i, fut in enumerate(refs):
+            check_records(orc, kw["L"], res["rough"], fut.result(), i, times, tag=str(kw))
+    return results
+
+
+def test_packed_whole_rings_c2_match_oracle(orc, pool):
+    # several requests of 2^17-site whole rings (two slots per lane) with the
+    # same kernel shape: the request loop packs them into shared launches
+    reqs = []
+    for i in range(6):
+        kw = dict(L=1 << 17, seed=30 + i, stream=i, windows=1)
+        if i % 2:
+            kw.update(p=1.0, q=0.0, slow_frac=0.1, slow_factor=0.5)
+        else:
+            kw.update(p=1.0, q=0.0)
+        reqs.append((kw, 1 + i % 3, [0, 2, 5, 11 + i], 11 + i))
+    _server_vs_oracle(orc, pool, reqs, quantum_mcs=3, max_active=16)
+
+
+def test_served_mix_at_benchmark_parameters_matches_oracle(orc, pool):
+    # requests drawn like the served mix (L = 64 ceil(2^x / 64), x ~ U[10, 26];
+    # KPZ / EW / disorder), with the work of each capped so that the oracle
+    # can check every sample, through the request loop at the benchmark's
+    # serving parameters: whole rings of every slot count and windowed rings
+    # up to 2^26 sites
+    mix = W.served_mix(14, 1e9, seed=21, max_attempts=2.0**26, log2_L=(10, 26),
+                       log10_t=(0.0, 3.7), log2_samples=(0, 3))
+    reqs = [(r.kwargs(), r.samples, r.times, r.t_max) for r in mix]
+    # the mix's longest rings: 64 * ceil(2^25.6 / 64) sites, windowed
+    big = 64 * -(-int(2 ** 25.6) // 64)
+    reqs.append((dict(W.MODELS["disorder"], L=big, seed=91, stream=40), 1, [0, 1, 2], 2))
+    # and one multi-quantum request of every model
+    for k, name in enumerate(sorted(W.MODELS)):
+        kw = dict(W.MODELS[name], L=4096 + 64 * k, seed=77, stream=k)
+        reqs.append((kw, 2, W.geometric_times(4500), 4500))
+    _server_vs_oracle(orc, pool, reqs, quantum_mcs=2000, max_active=64)

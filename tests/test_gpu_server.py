@@ -65,11 +65,22 @@ def test_packed_small_requests_equal_alone():
         reqs.append((kw, 1 + i % 4, [0, 3, 17, 40 + i]))
     srv = A.Server(quantum_mcs=11, max_active=32)
     tickets = [srv.submit(A.make_params(samples=n, **kw), times, times[-1]) for kw, n, times in reqs]
+    packed = 0
     for (kw, n, times), t in zip(reqs, tickets):
         res = srv.wait(t, timeout_s=120)
         assert res["status"] == 0
         for x, y in zip(res["rough"], alone(kw, n, times)):
             assert same(x, y), kw
+        # the result echoes the schedule and plan the request ran with
+        sim = A.Simulation(A.make_params(samples=n, **kw))
+        assert res["params"]["cell_log2"] == sim.params.cell_log2 == 6
+        assert res["params"]["subsweeps"] == sim.params.subsweeps
+        assert res["params"]["rbits"] == sim.params.rbits
+        assert res["plan"] == sim.plan()
+        sim.close()
+        assert 1 <= res["quanta"] and res["packed_quanta"] <= res["quanta"]
+        packed += res["packed_quanta"]
+    assert packed > 0
     srv.close()
 
 
