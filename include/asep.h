@@ -61,7 +61,8 @@ enum {
     ASEP_E_PENDING = -6,     /* the request has not finished yet */
     ASEP_E_CANCELLED = -7,   /* the request was cancelled */
     ASEP_E_TIMEOUT = -8,     /* asep_wait ran out of time */
-    ASEP_E_NOTFOUND = -9     /* unknown ticket */
+    ASEP_E_NOTFOUND = -9,    /* unknown ticket */
+    ASEP_E_TOO_LARGE = -10   /* larger than the fixed workspace of asep_run_noalloc */
 };
 
 enum { ASEP_MODEL_RING = 0, ASEP_MODEL_TWO_LANE = 1 };
@@ -223,6 +224,32 @@ int asep_run(asep_sim* s, const uint64_t* times, uint32_t n_times, asep_rough* o
  * and all at or before times[0]. */
 int asep_run_batch(asep_sim* const* sims, uint32_t n_sims, const uint64_t* times,
                    uint32_t n_times, asep_rough* const* outs);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): a whole
+ * run -- asep_create_ext on state_dev, asep_run through times[0..n_times),
+ * asep_destroy -- that allocates nothing, host or device.
+ *   state_dev: the samples x planes x L/64 state words (at least
+ *     state_bytes >= that many bytes, asep_buffer_sizes' state size); the call
+ *     initialises them from p and leaves the state at times[n_times-1] there.
+ *   times: host array, ascending absolute MCS (n_times may be 0: only the
+ *     initialisation runs).
+ *   out_dev: device array of n_times x samples asep_rough (time-major), the
+ *     same values asep_run returns (integers exact, w2 formed on the device
+ *     from the exact numerator).
+ * Everything else the run needs (quenched planes, hop counters, record
+ * staging, the second state buffer of windowed plans) lives in one fixed
+ * device workspace of ASEP_NOALLOC_SCRATCH_BYTES per GPU, held from the
+ * first call on that GPU until the process ends; a run needing more returns
+ * ASEP_E_TOO_LARGE.  All work is queued on hip_stream (NULL = the null
+ * stream) and the call returns without waiting for it.  Calls on one GPU share
+ * the workspace: calls whose work overlaps on the device (other streams or
+ * threads, before the previous call's work has finished) race and give
+ * undefined results; calls queued on one stream are ordered and safe. */
+#define ASEP_NOALLOC_SCRATCH_BYTES (32u << 20)
+int asep_run_noalloc(const asep_params* p, uint64_t* state_dev, size_t state_bytes,
+                     void* hip_stream, const uint64_t* times, uint32_t n_times,
+                     asep_rough* out_dev);
 
 /* Copy one sample's state words (planes x L/64 uint64, lane A first) to or
  * from host memory; n_words must equal planes x L/64.  Synchronises. */

@@ -24,6 +24,8 @@ ASEP_E_PENDING = -6
 ASEP_E_CANCELLED = -7
 ASEP_E_TIMEOUT = -8
 ASEP_E_NOTFOUND = -9
+ASEP_E_TOO_LARGE = -10
+NOALLOC_SCRATCH_BYTES = 32 << 20
 ASEP_MODEL_RING = 0
 ASEP_MODEL_TWO_LANE = 1
 ASEP_INIT_FLAT = 0
@@ -161,6 +163,8 @@ SIGNATURES = {
     "asep_sweep": (_i32, [_vp, _u64]),
     "asep_roughness": (_i32, [_vp, _P(asep_rough)]),
     "asep_run": (_i32, [_vp, _P(_u64), _u32, _P(asep_rough)]),
+    "asep_run_noalloc": (_i32, [_P(asep_params), _vp, ctypes.c_size_t, _vp, _P(_u64), _u32,
+                                 _vp]),
     "asep_run_batch": (_i32, [_P(_vp), _u32, _P(_u64), _u32, _P(_P(asep_rough))]),
     "asep_read_state": (_i32, [_vp, _u32, _P(_u64), _u64]),
     "asep_write_state": (_i32, [_vp, _u32, _P(_u64), _u64]),

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libasep.so")
 SOURCES = ["asep_kernels.hip", "asep_sweep_plain.hip", "asep_sweep_disorder.hip",
-           "asep_sweep_two_lane.hip", "asep_host.cpp", "asep_server.cpp", "asep_server_hip.cpp"]
+           "asep_sweep_two_lane.hip", "asep_host.cpp", "asep_server.cpp", "asep_server_hip.cpp", "asep_noalloc.hip"]
 ARCH = "gfx950"
 
 

@@ -214,31 +214,27 @@ static int resolve(const asep_params* in, int dev, Resolved* r) {
     // two-sub-lattice update compares a 24-bit uniform per pair
     const int B = sca ? 24 : 32 - (int)sc.lam - ebits;
     uint64_t TB[4] = {0, 0, 0, 0};
-    std::vector<uint64_t> used;
+    uint32_t n_used;  // thresholds in use: TB[0 .. n_used)
     if (!two) {
         TB[0] = lower_prob(P.p, B);
         TB[1] = lower_prob(P.q, B);
         TB[2] = lower_prob(P.slow_factor * P.p, B);
         TB[3] = lower_prob(P.slow_factor * P.q, B);
-        used = {TB[0], TB[1]};
-        if (P.slow_frac > 0) {
-            used.push_back(TB[2]);
-            used.push_back(TB[3]);
-        }
+        n_used = P.slow_frac > 0 ? 4 : 2;
     } else {
         TB[0] = lower_prob(P.p, B);
         TB[1] = lower_prob(P.q, B);
         TB[2] = lower_prob(P.lane_rate, B);
-        used = {TB[0], TB[1], TB[2]};
+        n_used = 3;
         if (sca) {
             TB[3] = lower_prob(P.slow_factor * P.lane_rate, B);  // marked sites
-            if (P.slow_frac > 0) used.push_back(TB[3]);
+            if (P.slow_frac > 0) n_used = 4;
         }
     }
     auto exact_at = [&](int b) {
         const uint64_t unit = uint64_t(1) << (B - b);
-        for (uint64_t t : used)
-            if (t % unit != 0) return false;
+        for (uint32_t i = 0; i < n_used; ++i)
+            if (TB[i] % unit != 0) return false;
         return true;
     };
     int b;
@@ -587,7 +583,8 @@ static int sim_init(asep_sim* s) {
     if (r.mplanes)
         HIP_OR_FAIL(launch_init_masks(s->masks, r.n_real, r.mplanes, r.mtags, r.nw, r.T_mask,
                                       r.P.seed, r.P.stream, r.real0, s->stream));
-    HIP_OR_FAIL(hipMemsetAsync(s->hops, 0, (size_t)r.P.samples * 8, s->stream));
+    // a fill kernel rather than a memset node, so that the work can be captured
+    HIP_OR_FAIL(launch_zero_u64((uint64_t*)s->hops, r.P.samples, s->stream));
     return ASEP_OK;
 }
 
@@ -1053,6 +1050,45 @@ int sim_pack_commit(asep_sim* s, uint64_t t_end, uint32_t n, Record* host_out, h
 
 int device_error(hipError_t e, const char* where) { return device_fail(e, where); }
 
+int sim_run_scratch(const asep_params* p, uint64_t* state, size_t state_bytes, hipStream_t st,
+                    void* scratch, size_t scratch_bytes, const uint64_t* times, uint32_t n,
+                    asep_rough* out_dev, RoughOut to_rough) {
+    if (!state || !scratch || !to_rough || (n && (!times || !out_dev))) return ASEP_E_INVAL;
+    asep_sim s;  // on this frame; its vectors stay empty (profiling is off)
+    int rc = resolve(p, current_device(), &s.r);
+    if (rc == ASEP_OK) rc = choose_plan(s.r, &s.plan);
+    if (rc) return rc;
+    const size_t need_state = (size_t)s.r.P.samples * s.r.planes * s.r.nw * 8;
+    size_t o_masks, o_hops, o_rec, o_recg, o_alt, need_aux;
+    aux_layout(s.r, s.plan, &o_masks, &o_hops, &o_rec, &o_recg, &o_alt, &need_aux);
+    if (state_bytes < need_state) return ASEP_E_INVAL;
+    if (need_aux > scratch_bytes) return ASEP_E_TOO_LARGE;
+    unsigned char* a = (unsigned char*)scratch;
+    s.stream = st;
+    s.words = state;
+    s.masks = s.r.mplanes ? (uint64_t*)(a + o_masks) : nullptr;
+    s.hops = (int64_t*)(a + o_hops);
+    s.rec = (Record*)(a + o_rec);
+    s.alt = s.plan.seg ? (uint64_t*)(a + o_alt) : nullptr;
+    s.rec_cap = kRecCap;
+    rc = check_times(&s, times, n);
+    if (rc) return rc;
+    // every scratch region is rewritten before it is read: the quenched
+    // planes and hop counters by the initialisation, the records by the
+    // measurements, the second state buffer by the first window launch
+    rc = sim_init(&s);
+    if (rc) return rc;
+    const uint32_t R = s.r.P.samples;
+    for (uint32_t done = 0; done < n;) {
+        const uint32_t m = std::min(kRecCap, n - done);
+        rc = enqueue_to(&s, times[done + m - 1], times + done, m, nullptr);
+        if (rc) return rc;
+        HIP_OR_FAIL(to_rough(s.rec, out_dev + (size_t)done * R, m * R, s.r.P.L, st));
+        done += m;
+    }
+    return ASEP_OK;
+}
+
 }  // namespace asep
 
 extern "C" int asep_read_state(asep_sim* s, uint32_t sample, uint64_t* words, uint64_t n_words) {
@@ -1154,6 +1190,8 @@ extern "C" const char* asep_strerror(int code) {
         case ASEP_E_CANCELLED: return "cancelled";
         case ASEP_E_TIMEOUT: return "timed out";
         case ASEP_E_NOTFOUND: return "unknown ticket";
+        case ASEP_E_TOO_LARGE:
+            return "run needs more scratch than the fixed no-allocation workspace holds";
         default: return "unknown error";
     }
 }

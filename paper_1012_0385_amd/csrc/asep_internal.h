@@ -76,6 +76,8 @@ hipError_t launch_init_masks(uint64_t* masks, uint32_t n_real, uint32_t mplanes,
                              uint32_t key1, uint32_t real0, hipStream_t st);
 hipError_t launch_rough(const uint64_t* words, const int64_t* hops, Record* rec, uint32_t R,
                         uint32_t planes, uint32_t nw, hipStream_t st);
+// words[0 .. n) = 0 (a kernel, not a memset node).
+hipError_t launch_zero_u64(uint64_t* words, uint64_t n, hipStream_t st);
 
 // Sweep launch: `one` describes the whole launch when descs == nullptr;
 // otherwise descs[0..n_desc) (device memory, sorted by wg_begin) do.  With
@@ -133,4 +135,14 @@ int sim_pack_prepare(asep_sim* s, uint64_t t_end, const uint64_t* times, uint32_
                      SimDesc* d);
 int sim_pack_commit(asep_sim* s, uint64_t t_end, uint32_t n, Record* host_out, hipStream_t st);
 int device_error(hipError_t e, const char* where);
+// A whole run (initialisation, then advance and measure through times[0..n))
+// on the caller's state buffer and stream, with every other buffer carved
+// from `scratch` (scratch_bytes long); nothing is allocated.  Records go to
+// `out_dev` (device memory, n x samples asep_rough) through the device
+// conversion `to_rough`.  ASEP_E_TOO_LARGE if the run needs more scratch.
+typedef hipError_t (*RoughOut)(const Record* rec, asep_rough* out, uint32_t n, uint64_t L,
+                               hipStream_t st);
+int sim_run_scratch(const asep_params* p, uint64_t* state, size_t state_bytes, hipStream_t st,
+                    void* scratch, size_t scratch_bytes, const uint64_t* times, uint32_t n,
+                    asep_rough* out_dev, RoughOut to_rough);
 }  // namespace asep

@@ -158,7 +158,23 @@ __global__ __launch_bounds__(256) void k_rough(const uint64_t* __restrict__ word
     }
 }
 
+__global__ void k_zero_u64(uint64_t* __restrict__ words, uint64_t n) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        words[i] = 0;
+}
+
 }  // namespace
+
+hipError_t launch_zero_u64(uint64_t* words, uint64_t n, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    const uint32_t block = 256;
+    const uint64_t want = (n + block - 1) / block;
+    const uint32_t grid = (uint32_t)(want < 4096 ? want : 4096);
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_zero_u64, dim3(grid), dim3(block), 0, st, words, n);
+    return hipGetLastError();
+}
 
 hipError_t launch_init_state(uint64_t* words, uint32_t R, uint32_t planes, uint32_t nw,
                              uint32_t init, uint64_t T_init, uint32_t key0, uint32_t key1,
