@@ -102,7 +102,11 @@ typedef struct asep_params {
                           0 (or negative) = the fewest that keep every threshold
                           exact, n >= 1 = exactly n (ASEP_E_INVAL if a threshold
                           is not exact at n bits); an explicit 0 would always
-                          equal the automatic choice, so 0 means automatic */
+                          equal the automatic choice, so 0 means automatic.
+                          Two lanes under the shifted schedule: the hop
+                          thresholds only; a lane change compares its own
+                          32-bit draw at the fewest bits that keep the lane
+                          rate exact */
     uint32_t windows;  /* launch shape only, never results: 0 = from the tuning
                           table, else automatic; 1 = each ring whole in one
                           workgroup, n >= 2 = each ring cut into n windows */
@@ -179,7 +183,10 @@ enum {
     ASEP_LOOP_F4B2 = 3,      /* 4 per draw, 2 compared bits */
     ASEP_LOOP_F1 = 4,        /* 1 per draw, compared bits at run time */
     ASEP_LOOP_F4B0_LANES = 5,/* two lanes, 64 attempts: 4 per draw, no compared bit */
-    ASEP_LOOP_SUBLATTICE = 6 /* the paper's two-sub-lattice update */
+    ASEP_LOOP_SUBLATTICE = 6,/* the paper's two-sub-lattice update */
+    ASEP_LOOP_H6B0 = 7,      /* ell = 32, 2 sub-sweeps: a slot's halves are two cells,
+                                6 fields per draw, no compared bit */
+    ASEP_LOOP_H5B1 = 8       /* ell = 32, 2 sub-sweeps: 5 fields per draw, 1 compared bit */
 };
 typedef struct asep_plan {
     uint32_t windows;        /* 1: each ring whole in one workgroup; n >= 2: windows per ring */

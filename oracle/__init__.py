@@ -72,6 +72,7 @@ class _Sched(ctypes.Structure):
         ("T_init", ctypes.c_uint64),
         ("T_slow", ctypes.c_uint64),
         ("T_turn", ctypes.c_uint64),
+        ("bc", ctypes.c_uint32),
     ]
 
 

@@ -81,6 +81,7 @@ void orc_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
 #define TAG_DIS_Q 5u
 #define TAG_TURN 6u
 #define TAG_RSU 7u
+#define TAG_CHANGE 9u
 
 static void draw(const orc_params *P, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                  uint32_t out[4]) {
@@ -197,12 +198,17 @@ int orc_lower(const orc_params *P, orc_sched *S) {
             t[nt++] = S->TB[3];
         }
     } else {
-        S->TB[0] = orc_threshold(P->p, S->B);         /* lane A hop right */
-        S->TB[1] = orc_threshold(P->q, S->B);         /* lane B hop left  */
-        S->TB[2] = orc_threshold(P->lane_rate, S->B); /* lane change      */
+        S->TB[0] = orc_threshold(P->p, S->B); /* lane A hop right */
+        S->TB[1] = orc_threshold(P->q, S->B); /* lane B hop left  */
         t[nt++] = S->TB[0];
         t[nt++] = S->TB[1];
-        t[nt++] = S->TB[2];
+        /* A lane change is decided by a 32-bit draw of its own (see
+         * subsweep_two_lane), compared at the fewest bits that keep its
+         * threshold exact. */
+        S->TB[2] = orc_threshold(P->lane_rate, 32);
+        uint32_t c = 0;
+        while (c < 32 && S->TB[2] % ((uint64_t)1 << (32 - c)) != 0) ++c;
+        S->bc = c;
     }
     /* precision b: the fewest low-order bits such that every threshold in use
      * is an exact multiple of 2^(B-b); then r < T at b bits has the same law. */
@@ -222,6 +228,7 @@ int orc_lower(const orc_params *P, orc_sched *S) {
     }
     S->b = (uint32_t)b;
     for (int i = 0; i < 4; ++i) S->T[i] = S->TB[i] >> (S->B - b);
+    if (two) S->T[2] = S->TB[2] >> (32 - S->bc);
     S->w = S->lam + S->ebits + S->b;
     S->A = 32 / S->w;
     S->per_block = 4 * S->A;
@@ -341,7 +348,21 @@ static void subsweep_ring(const orc_params *P, const orc_sched *S, uint32_t samp
  * change lane at a turning point when the other lane's site is empty.  The
  * event e of each attempt is 0: A hop on bond (x,x+1); 1: B hop on bond
  * (x,x+1) from x+1 to x; 2: A->B at x; 3: B->A at x.  Bond events with
- * j = ell-1 are no-ops; site events use every j. */
+ * j = ell-1 are no-ops; site events use every j.  Hops compare the field's r
+ * with their thresholds.  A lane-change attempt that finds a turning point,
+ * a particle on its side and a hole on the other is the cell's c-th
+ * candidate of the sub-sweep (counted from 0 in attempt order); it draws the
+ * 32-bit word c mod 4 of the block at counter (k, lo32(g), CHANGE << 28 |
+ * (c / 4) << 16 | hi16(g), sample) and moves if the word's top bc bits are
+ * below the lane-change threshold. */
+static uint32_t change_word(const orc_params *P, uint32_t sample, uint64_t k, uint64_t g,
+                            uint32_t c) {
+    uint32_t out[4];
+    uint32_t c2 = (TAG_CHANGE << 28) | ((c / 4) << 16) | (uint32_t)((g >> 32) & 0xFFFFu);
+    draw(P, (uint32_t)k, (uint32_t)(g & 0xFFFFFFFFu), c2, sample, out);
+    return out[c % 4];
+}
+
 static void subsweep_two_lane(const orc_params *P, const orc_sched *S, uint32_t sample, uint64_t g,
                               uint8_t *s, const uint8_t *turn, int64_t *J) {
     const uint64_t L = P->L;
@@ -353,6 +374,7 @@ static void subsweep_two_lane(const orc_params *P, const orc_sched *S, uint32_t 
         const uint64_t base = (sigma + k * S->ell) % L;
         uint32_t blockbuf[4];
         uint32_t cached = 0xFFFFFFFFu;
+        uint32_t cand = 0; /* lane-change candidates of this cell so far */
         for (uint32_t m = 0; m < S->a; ++m) {
             uint32_t j, e, r;
             attempt_fields(P, S, sample, k, g, m, blockbuf, &cached, &j, &e, &r);
@@ -370,15 +392,16 @@ static void subsweep_two_lane(const orc_params *P, const orc_sched *S, uint32_t 
                     Bl[x] = 1;
                     *J -= 1;
                 }
-            } else if (e == 2) {
-                if (turn[x] && A[x] == 1 && Bl[x] == 0 && (uint64_t)r < S->T[2]) {
-                    A[x] = 0;
-                    Bl[x] = 1;
-                }
             } else {
-                if (turn[x] && Bl[x] == 1 && A[x] == 0 && (uint64_t)r < S->T[2]) {
-                    Bl[x] = 0;
-                    A[x] = 1;
+                uint8_t *from = (e == 2) ? A : Bl;
+                uint8_t *to = (e == 2) ? Bl : A;
+                if (turn[x] && from[x] == 1 && to[x] == 0) {
+                    uint32_t u = change_word(P, sample, k, g, cand++);
+                    uint64_t rc = S->bc ? ((uint64_t)u >> (32 - S->bc)) : 0;
+                    if (rc < S->T[2]) {
+                        from[x] = 0;
+                        to[x] = 1;
+                    }
                 }
             }
         }

@@ -40,6 +40,8 @@ typedef struct {
     uint64_t TB[4]; /* thresholds at B bits */
     uint64_t T[4];  /* thresholds at b bits: ring {p, q, r p, r q}; two-lane {A, B, lane} */
     uint64_t T_init, T_slow, T_turn; /* 32-bit thresholds */
+    uint32_t bc;    /* two lanes, shifted schedule: bits compared for a lane change
+                       (T[2] is the lane-change threshold at bc bits) */
 } orc_sched;
 
 typedef struct {

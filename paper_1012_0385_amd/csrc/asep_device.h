@@ -160,6 +160,15 @@ struct CellCtx {
     // 2+b and (with backward hops) the backward mark at bit 3+b hop;
     // repeated likewise above the bits in use.
     uint32_t lutD;
+    // Two lanes: lane-change draws (tag | hi16(g)), their compared bits,
+    // and the outcome table of the fast loop: bit 32 e1 + 16 e0 + [a_x
+    // a_x+1 b_x b_x+1] (bit 0 first) says, for events e = 2 e1 + e0 0 and 1,
+    // whether the hop (A right, B left) fires, and for events 2 and 3
+    // whether the lane change (A -> B, B -> A) finds a particle on its side
+    // and a hole on the other.
+    uint32_t c2c, bc;
+    uint64_t Tw;  // lane change: a draw u moves iff u < Tw (T2 << (32 - bc))
+    uint64_t lut2;
 };
 
 // Generic single-lane cell: any cell size ell <= 64 located at bit `bb` of
@@ -300,17 +309,118 @@ __device__ __forceinline__ int32_t cell_ring_fast(uint64_t& x, uint64_t m0, uint
     return Q0 ? dj / 3 : dj;
 }
 
+// Single lane, ell = 32, two sub-sweeps per MCS (16 attempts per cell per
+// sub-sweep): the slot's two cells are its 32-bit halves (cells 2w and
+// 2w + 1), each updated with 32-bit operations, and their attempt chains
+// are independent, so one lane runs two of them side by side.  A fields per
+// 32-bit word, BB (<= 2) compared bits; the outcome is one bit of lutP
+// indexed by the pair and the compared bits, and the arithmetic shift makes
+// j = 31 (the bond leaving the cell) a no-op, as in cell_ring_fast.
+template <int A, int BB, bool Q0, int NA>
+__device__ __forceinline__ int32_t cell_half_fast(uint64_t& x, const CellCtx& c) {
+    constexpr int PER = 4 * A;
+    constexpr int NB = (NA + PER - 1) / PER;
+    static_assert(BB >= 0 && BB <= 2 && A * (5 + BB) <= 32, "field layout");
+    uint32_t h0 = (uint32_t)x, h1 = (uint32_t)(x >> 32);
+    int32_t d0 = 0, d1 = 0;
+#pragma unroll
+    for (int blk = 0; blk < NB; ++blk) {
+        const uint32_t c2 = c.c2b | ((uint32_t)blk << 16);
+        const Blk r0 = philox(c.k, c.glo, c2, c.sample, c.k0, c.k1);
+        const Blk r1 = philox(c.k + 1u, c.glo, c2, c.sample, c.k0, c.k1);
+#pragma unroll
+        for (int wd = 0; wd < 4; ++wd) {
+#pragma unroll
+            for (int sl = 0; sl < A; ++sl) {
+                if (blk * PER + wd * A + sl >= NA) continue;
+                constexpr uint32_t W = 5u + (uint32_t)BB;
+                const uint32_t sh = (uint32_t)sl * W;
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const uint32_t u = q ? r1.v[wd] : r0.v[wd];
+                    uint32_t& h = q ? h1 : h0;
+                    int32_t& d = q ? d1 : d0;
+                    const uint32_t j = bfe(u, sh + (uint32_t)BB, 5);
+                    const uint32_t sx = (uint32_t)((int32_t)h >> j);
+                    uint32_t off = sx;
+                    if (BB > 0) {
+                        const uint32_t rs = sh >= 2 ? u >> (sh - 2) : u << (2 - sh);
+                        off = insert_low2(sx, rs);
+                    }
+                    const uint32_t F = (uint32_t)__builtin_amdgcn_sbfe((int32_t)c.lutP, off, 1);
+                    h = xor_masked(h, 3u << j, F);
+                    d += (int32_t)F;
+                    if (!Q0) d += (int32_t)(F & ~sx & 2u);
+                }
+            }
+        }
+    }
+    x = (uint64_t)h0 | ((uint64_t)h1 << 32);
+    return Q0 ? -(d0 + d1) : d0 + d1;
+}
+
 // Two lanes (Sec. 3): events 0 = A hops right on (x, x+1), 1 = B hops left
 // from x+1 to x, 2 = A->B at x, 3 = B->A at x (turning point, other lane
 // empty).  Bond events at j = ell-1 are no-ops; site events use every j.
+//
+// A lane change is decided by a 32-bit draw of its own: the cell's c-th
+// candidate of the sub-sweep (a lane-change attempt at a turning point with
+// a particle on its side and a hole on the other, counted from 0 in attempt
+// order) takes word c mod 4 of Philox block (k, lo32(g), change tag |
+// (c / 4) << 16 | hi16(g), sample) and moves when the word's top bc bits are
+// below T2.  Candidates are rare (a fraction of a percent of the attempts in
+// the two-lane workload): a cell draws its first block up front, the fast
+// loop decides at most four candidates from it, and a lane whose cell meets
+// a fifth redoes the cell's sub-sweep with the generic loop, which draws
+// every further block as it needs it.
+struct ChangeDraws {
+    uint32_t u0, u1, u2, u3;
+    uint32_t n;  // candidates so far
+};
+
+__device__ __forceinline__ void change_begin(ChangeDraws& d, const CellCtx& c) {
+    d.n = 0;
+    d.u0 = d.u1 = d.u2 = d.u3 = 0;
+    if (c.bc) {
+        const Blk r = philox(c.k, c.glo, c.c2c, c.sample, c.k0, c.k1);
+        d.u0 = r.v[0];
+        d.u1 = r.v[1];
+        d.u2 = r.v[2];
+        d.u3 = r.v[3];
+    }
+}
+
+// Decision of the next candidate.  LATE: draw blocks past the first as
+// needed; otherwise a fifth candidate sets `over` (its outcome is not used).
+template <bool LATE>
+__device__ __forceinline__ bool change_accept(ChangeDraws& d, const CellCtx& c, bool& over) {
+    const uint32_t n = d.n++;
+    if (c.bc == 0) return c.T2 != 0;
+    uint32_t u;
+    if (n < 4) {
+        u = n == 0 ? d.u0 : n == 1 ? d.u1 : n == 2 ? d.u2 : d.u3;
+    } else if (LATE) {
+        const Blk r = philox(c.k, c.glo, c.c2c | ((n >> 2) << 16), c.sample, c.k0, c.k1);
+        const uint32_t q = n & 3u;
+        u = q == 0 ? r.v[0] : q == 1 ? r.v[1] : q == 2 ? r.v[2] : r.v[3];
+    } else {
+        over = true;
+        return false;
+    }
+    return (u >> (32u - c.bc)) < c.T2;
+}
+
+template <bool LATE>
 __device__ __forceinline__ void two_lane_event(uint64_t& xa, uint64_t& xb, uint32_t pa,
                                                uint32_t pb, uint32_t tt, uint32_t e, uint32_t rv,
                                                bool live, uint32_t pos, const CellCtx& c,
-                                               int32_t& dj) {
+                                               ChangeDraws& cd, bool& over, int32_t& dj) {
     const bool hopA = e == 0u && live && pa == 1u && rv < c.T0;
     const bool hopB = e == 1u && live && pb == 2u && rv < c.T1;
     const uint32_t a0 = pa & 1u, b0 = pb & 1u;
-    const bool chg = e >= 2u && tt && a0 != b0 && a0 == (e == 2u ? 1u : 0u) && rv < c.T2;
+    const bool cand = e >= 2u && tt && a0 != b0 && a0 == (e == 2u ? 1u : 0u);
+    bool chg = false;
+    if (cand) chg = change_accept<LATE>(cd, c, over);
     const uint32_t ch = chg ? 1u : 0u;
     xa ^= (uint64_t)(hopA ? 3u : ch) << pos;
     xb ^= (uint64_t)(hopB ? 3u : ch) << pos;
@@ -325,9 +435,11 @@ __device__ __forceinline__ int32_t cell_two_lane_generic(uint64_t& xa, uint64_t&
     const uint32_t rmask = (c.b >= 32) ? 0xFFFFFFFFu : ((1u << c.b) - 1u);
     int32_t dj = 0;
     uint32_t m = 0;
+    ChangeDraws cd;
+    change_begin(cd, c);
+    bool over = false;  // never set: every block is drawn as needed
     for (uint32_t blk = 0; blk < c.nblk; ++blk) {
         const Blk r = philox(c.k, c.glo, c.c2b | (blk << 16), c.sample, c.k0, c.k1);
-#pragma unroll
         for (int wd = 0; wd < 4; ++wd) {
             const uint32_t u = r.v[wd];
             for (uint32_t sl = 0; sl < c.A && m < c.na; ++sl, ++m) {
@@ -339,7 +451,7 @@ __device__ __forceinline__ int32_t cell_two_lane_generic(uint64_t& xa, uint64_t&
                 const uint32_t pa = (uint32_t)(xa >> pos) & 3u;
                 const uint32_t pb = (uint32_t)(xb >> pos) & 3u;
                 const uint32_t tt = (uint32_t)(tm >> pos) & 1u;
-                two_lane_event(xa, xb, pa, pb, tt, e, rv, j != cmask, pos, c, dj);
+                two_lane_event<true>(xa, xb, pa, pb, tt, e, rv, j != cmask, pos, c, cd, over, dj);
             }
         }
     }
@@ -349,13 +461,20 @@ __device__ __forceinline__ int32_t cell_two_lane_generic(uint64_t& xa, uint64_t&
 // ell = 64, default schedule (NA attempts per cell per sub-sweep), A fields
 // per word and BB compared bits known at compile time (BB < 0: runtime); the
 // arithmetic-shift pair read makes bond events at j = 63 no-ops while site
-// events there stay live.
+// events there stay live.  With no compared bit (hop rates 0 or 1) the
+// pairs of both lanes and the event's low bit index the outcome tables:
+// the hop is one masked XOR per half of the hopping lane's word, and only
+// lane-change candidates (rare) take a branch for their draw.
 template <int A, int BB, int NA>
 __device__ __forceinline__ int32_t cell_two_lane_fast(uint64_t& xa, uint64_t& xb, uint64_t tm,
                                                        const CellCtx& c) {
     constexpr int PER = 4 * A;
     constexpr int NB = (NA + PER - 1) / PER;
     int32_t dj = 0;
+    ChangeDraws cd;
+    change_begin(cd, c);
+    bool over = false;
+    const uint64_t xa0 = xa, xb0 = xb;
 #pragma unroll
     for (int blk = 0; blk < NB; ++blk) {
         const Blk r = philox(c.k, c.glo, c.c2b | ((uint32_t)blk << 16), c.sample, c.k0, c.k1);
@@ -365,17 +484,68 @@ __device__ __forceinline__ int32_t cell_two_lane_fast(uint64_t& xa, uint64_t& xb
             for (int sl = 0; sl < A; ++sl) {
                 if (blk * PER + wd * A + sl >= NA) continue;
                 const uint32_t u = r.v[wd];
-                const uint32_t b = BB >= 0 ? (uint32_t)BB : c.b;
-                const uint32_t sh = BB >= 0 ? (uint32_t)(sl * (8 + BB)) : (uint32_t)sl * c.w;
-                const uint32_t rv = (BB == 0) ? 0u : bfe(u, sh, b);
-                const uint32_t e = bfe(u, sh + b, 2);
-                const uint32_t j = bfe(u, sh + b + 2, 6);
-                const uint32_t pa = (uint32_t)((int64_t)xa >> j) & 3u;
-                const uint32_t pb = (uint32_t)((int64_t)xb >> j) & 3u;
-                const uint32_t tt = (uint32_t)(tm >> j) & 1u;
-                two_lane_event(xa, xb, pa, pb, tt, e, rv, true, j, c, dj);
+                if constexpr (BB == 0) {
+                    const uint32_t sh = (uint32_t)sl * 8u;  // field [j(6) | e(2)]
+                    const uint32_t j = bfe(u, sh + 2u, 6);
+                    // state-independent: event bits as masks, the table half
+                    // of e1, the turning bit at j, the pair mask
+                    const uint32_t E0 = (uint32_t)__builtin_amdgcn_sbfe((int32_t)u, sh, 1);
+                    const uint32_t E1 = (uint32_t)__builtin_amdgcn_sbfe((int32_t)u, sh + 1u, 1);
+                    const uint32_t lw = (uint32_t)(c.lut2 >> (bfe(u, sh + 1u, 1) << 5));
+                    const uint32_t TT =
+                        (uint32_t)__builtin_amdgcn_sbfe((int32_t)(uint32_t)(tm >> j), 0, 1);
+                    const uint32_t eh = sh >= 4u ? u >> (sh - 4u) : u << (4u - sh);
+                    const uint64_t M = 3ull << j;
+                    // the state chain: both lanes' pairs, then one table bit
+                    const int64_t sa = (int64_t)xa >> j;
+                    const int64_t sb = (int64_t)xb >> j;
+                    const uint32_t v = insert_low2((uint32_t)sa, (uint32_t)sb << 2);
+                    const uint32_t idx = __builtin_amdgcn_bitop3_b32(v, eh, 0xFu, 0xE4);
+                    const uint32_t F = (uint32_t)__builtin_amdgcn_sbfe((int32_t)lw, idx, 1);
+                    // F & ~E0 & ~E1, F & E0 & ~E1, F & E1 & TT (the table
+                    // index of a three-input op is src0 << 2 | src1 << 1 | src2)
+                    const uint32_t FA = __builtin_amdgcn_bitop3_b32(F, E0, E1, 0x10);
+                    const uint32_t FB = __builtin_amdgcn_bitop3_b32(F, E0, E1, 0x40);
+                    const uint32_t FC = __builtin_amdgcn_bitop3_b32(F, E1, TT, 0x80);
+                    xa = ((uint64_t)xor_masked((uint32_t)(xa >> 32), (uint32_t)(M >> 32), FA) << 32) |
+                         xor_masked((uint32_t)xa, (uint32_t)M, FA);
+                    xb = ((uint64_t)xor_masked((uint32_t)(xb >> 32), (uint32_t)(M >> 32), FB) << 32) |
+                         xor_masked((uint32_t)xb, (uint32_t)M, FB);
+                    dj += (int32_t)FB - (int32_t)FA;  // A right: +1, B left: -1
+                    // add now: summed later, every attempt's outcome would
+                    // stay live across the lane-change branches below
+                    asm volatile("" : "+v"(dj));
+                    if (FC) {
+                        // the next of the four draws made up front (a
+                        // fifth candidate sends the cell to the replay)
+                        const uint32_t n = cd.n;
+                        const uint32_t uc = n == 0u ? cd.u0 : n == 1u ? cd.u1 : n == 2u ? cd.u2 : cd.u3;
+                        over |= n >= 4u;
+                        cd.n = n + 1u;
+                        if ((uint64_t)uc < c.Tw) {
+                            const uint64_t m1 = 1ull << j;
+                            xa ^= m1;
+                            xb ^= m1;
+                        }
+                    }
+                } else {
+                    const uint32_t b = BB >= 0 ? (uint32_t)BB : c.b;
+                    const uint32_t sh = BB >= 0 ? (uint32_t)(sl * (8 + BB)) : (uint32_t)sl * c.w;
+                    const uint32_t rv = bfe(u, sh, b);
+                    const uint32_t e = bfe(u, sh + b, 2);
+                    const uint32_t j = bfe(u, sh + b + 2, 6);
+                    const uint32_t pa = (uint32_t)((int64_t)xa >> j) & 3u;
+                    const uint32_t pb = (uint32_t)((int64_t)xb >> j) & 3u;
+                    const uint32_t tt = (uint32_t)(tm >> j) & 1u;
+                    two_lane_event<false>(xa, xb, pa, pb, tt, e, rv, true, j, c, cd, over, dj);
+                }
             }
         }
+    }
+    if (over) {  // a fifth lane-change candidate: redo the cell exactly
+        xa = xa0;
+        xb = xb0;
+        dj = cell_two_lane_generic(xa, xb, tm, 0, 6, c);
     }
     return dj;
 }
@@ -563,6 +733,8 @@ enum Variant : int {
     kF1 = 4,    // 1 field per word, threshold bits at run time
     kF4B0 = 5,  // two lanes: 4 fields per word, no threshold bits
     kSca = 6,   // the paper's sub-lattice updates (both models, every slot shape)
+    kH6B0 = 7,  // ell = 32, two sub-sweeps: 6 fields per word, no threshold bits
+    kH5B1 = 8,  // ell = 32, two sub-sweeps: 5 fields per word, 1 threshold bit
 };
 
 template <int V>
@@ -588,6 +760,14 @@ struct VarInfo<kF1> {
 template <>
 struct VarInfo<kF4B0> {
     static constexpr int A = 4, BB = 0;
+};
+template <>
+struct VarInfo<kH6B0> {
+    static constexpr int A = 6, BB = 0;
+};
+template <>
+struct VarInfo<kH5B1> {
+    static constexpr int A = 5, BB = 1;
 };
 
 // Dynamic LDS of the sweep kernel, in this order:
@@ -691,7 +871,8 @@ template <int C, int MODEL, int V, bool Q0, bool MEAS, bool WU>
 __device__ __forceinline__ void sweep_body(const SimDesc& P) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int NPL = (MODEL == kTwoLane) ? 2 : 1;
-    constexpr bool FAST = V != kGeneric && V != kSca;
+    constexpr bool HALF = V == kH6B0 || V == kH5B1;
+    constexpr bool FAST = V != kGeneric && V != kSca && !HALF;
     constexpr int AV = VarInfo<V>::A;
     constexpr int BV = VarInfo<V>::BB;
 
@@ -760,6 +941,21 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
     cc.T3 = P.sc.T[3];
     cc.lutP = 0;
     cc.lutD = 0;
+    cc.c2c = 0;
+    cc.bc = P.sc.bc;
+    cc.Tw = (uint64_t)P.sc.T[2] << (32u - P.sc.bc);
+    cc.lut2 = 0;
+    if (MODEL == kTwoLane) {
+        for (uint32_t o = 0; o < 32; ++o) {
+            const uint32_t a0 = o & 1u, a1 = (o >> 1) & 1u, b0 = (o >> 2) & 1u,
+                           b1 = (o >> 3) & 1u, e0 = (o >> 4) & 1u;
+            const bool hop = e0 == 0 ? (a0 == 1u && a1 == 0u && P.sc.T[0] != 0)
+                                     : (b0 == 0u && b1 == 1u && P.sc.T[1] != 0);
+            const bool cand = e0 == 0 ? (a0 == 1u && b0 == 0u) : (a0 == 0u && b0 == 1u);
+            cc.lut2 |= (uint64_t)(hop ? 1u : 0u) << o;
+            cc.lut2 |= (uint64_t)(cand ? 1u : 0u) << (32 + o);
+        }
+    }
     if (P.sc.b <= 2) {
         const uint32_t b = P.sc.b;
         for (uint32_t o = 0; o < 32; ++o) {
@@ -1011,6 +1207,7 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
             }
             shift_to(sw & cmask);
             cc.c2b = (kTagAttempt << 28) | (uint32_t)((g >> 32) & 0xFFFFu);
+            cc.c2c = (kTagChange << 28) | (uint32_t)((g >> 32) & 0xFFFFu);
         }
         cc.glo = (uint32_t)g;
         int32_t dj = 0;
@@ -1054,6 +1251,9 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
                     } else {
                         d = sca_slot<Q0, MODEL == kDisorder>(xa, m0, m1, cc);
                     }
+                } else if constexpr (HALF) {
+                    cc.k = 2u * w;
+                    d = cell_half_fast<AV, BV, Q0, 16>(xa, cc);
                 } else if constexpr (FAST) {
                     cc.k = w;
                     if (MODEL == kTwoLane)
@@ -1224,6 +1424,16 @@ inline hipError_t launch_c(const SweepKernel& k, const SimDesc& one, const SimDe
                 case kF5B0: launch_q<MODEL, C, kF5B0>(k, one, descs, n_desc, grid, block, lds, st, ev0, ev1); return hipSuccess;
                 case kF4B1: launch_q<MODEL, C, kF4B1>(k, one, descs, n_desc, grid, block, lds, st, ev0, ev1); return hipSuccess;
                 case kF4B2: launch_q<MODEL, C, kF4B2>(k, one, descs, n_desc, grid, block, lds, st, ev0, ev1); return hipSuccess;
+                case kH6B0:
+                case kH5B1:
+                    if constexpr (MODEL == kPlain && C <= 8) {
+                        if (k.variant == kH6B0)
+                            launch_q<MODEL, C, kH6B0>(k, one, descs, n_desc, grid, block, lds, st, ev0, ev1);
+                        else
+                            launch_q<MODEL, C, kH5B1>(k, one, descs, n_desc, grid, block, lds, st, ev0, ev1);
+                        return hipSuccess;
+                    }
+                    return hipErrorInvalidValue;
                 case kF1:
                     if constexpr (C <= 8) {
                         launch_q<MODEL, C, kF1>(k, one, descs, n_desc, grid, block, lds, st, ev0, ev1);
@@ -1262,6 +1472,7 @@ inline bool variant_compiled(uint32_t C, uint32_t model, uint32_t variant) {
     if (variant == kSca) return model != kTwoLane || C <= 8;
     if (model == kTwoLane) return C <= 8 && (variant == kF4B0 || variant == kF1);
     if (variant == kF1) return C <= 8;  // one field per draw: 16 slots would spill
+    if (variant == kH6B0 || variant == kH5B1) return model == kPlain && C <= 8;
     return variant == kF5B0 || variant == kF4B1 || variant == kF4B2;
 }
 

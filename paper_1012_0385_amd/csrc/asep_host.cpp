@@ -221,15 +221,18 @@ static int resolve(const asep_params* in, int dev, Resolved* r) {
         TB[2] = lower_prob(P.slow_factor * P.p, B);
         TB[3] = lower_prob(P.slow_factor * P.q, B);
         n_used = P.slow_frac > 0 ? 4 : 2;
-    } else {
+    } else if (sca) {
         TB[0] = lower_prob(P.p, B);
         TB[1] = lower_prob(P.q, B);
         TB[2] = lower_prob(P.lane_rate, B);
-        n_used = 3;
-        if (sca) {
-            TB[3] = lower_prob(P.slow_factor * P.lane_rate, B);  // marked sites
-            if (P.slow_frac > 0) n_used = 4;
-        }
+        TB[3] = lower_prob(P.slow_factor * P.lane_rate, B);  // marked sites
+        n_used = P.slow_frac > 0 ? 4 : 3;
+    } else {
+        // hops compare the attempt field's bits; a lane change draws a 32-bit
+        // word of its own per candidate (below)
+        TB[0] = lower_prob(P.p, B);
+        TB[1] = lower_prob(P.q, B);
+        n_used = 2;
     }
     auto exact_at = [&](int b) {
         const uint64_t unit = uint64_t(1) << (B - b);
@@ -248,6 +251,14 @@ static int resolve(const asep_params* in, int dev, Resolved* r) {
     P.rbits = b;
     sc.b = (uint32_t)b;
     for (int i = 0; i < 4; ++i) sc.T[i] = (uint32_t)(TB[i] >> (B - b));
+    if (two && !sca) {
+        // lane change: threshold at 32 bits, compared at its fewest exact bits
+        const uint64_t tc = lower_prob(P.lane_rate, 32);
+        uint32_t c = 0;
+        while (c < 32 && tc % (uint64_t(1) << (32 - c)) != 0) ++c;
+        sc.bc = c;
+        sc.T[2] = (uint32_t)(tc >> (32 - c));
+    }
     if (sca) {
         sc.w = 0;
         sc.A = 0;
@@ -372,6 +383,12 @@ static SweepKernel pick_kernel(const Resolved& r, uint32_t C) {
             if (sc.A == 4 && sc.b == 0) v = 5;
             if (sc.A == 1) v = 4;
         }
+        if (v && sweep_variant_compiled(C, r.model, v)) k.variant = v;
+    } else if (sc.lam == 5 && sc.a == 16 && r.model == kPlain) {
+        // cells of 32 sites, two sub-sweeps: the slot's halves are two cells
+        uint32_t v = 0;
+        if (sc.A == 6 && sc.b == 0) v = 7;
+        if (sc.A == 5 && sc.b == 1) v = 8;
         if (v && sweep_variant_compiled(C, r.model, v)) k.variant = v;
     }
     k.q0 = !two && sc.T[1] == 0 && (r.model != kDisorder || sc.T[3] == 0);

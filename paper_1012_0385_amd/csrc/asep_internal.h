@@ -16,6 +16,7 @@ enum : uint32_t {
     kTagDisQ = 5,
     kTagTurn = 6,
     kTagSublattice = 8,
+    kTagChange = 9,
 };
 
 // One measurement of one ring (exact integers; W^2 is formed on the host).
@@ -37,6 +38,8 @@ struct Sched {
     uint32_t A;     // attempt fields per 32-bit word
     uint32_t nblk;  // Philox blocks per cell per sub-sweep
     uint32_t T[4];  // ring {p, q, r p, r q}; two lanes {A hop, B hop, lane change}
+    uint32_t bc;    // two lanes, shifted schedule: bits of a lane-change draw compared
+                    // with T[2] (0: T[2] is 0 = never or 1 = always)
     uint64_t T_init, T_slow, T_turn;  // 32-bit-draw thresholds (may equal 2^32)
 };
 

@@ -150,6 +150,34 @@ def test_two_lane(orc, L, S, lane_rate, turn):
     compare(orc, kw, [0, 2, 15], 5)
 
 
+@pytest.mark.parametrize("rates", [dict(p=1.0, q=0.0), dict(p=0.5, q=0.5, init=1, density=0.4)],
+                         ids=["kpz", "ew"])
+@pytest.mark.parametrize("shape", [dict(L=4096), dict(L=4160, windows=1),
+                                   dict(L=1 << 17, windows=4, window_sweeps=255),
+                                   dict(L=1 << 15, windows=3, window_sweeps=31)],
+                         ids=["small-packed", "ragged", "windows-K255", "windows-K31"])
+def test_half_word_cells(orc, rates, shape):
+    # cells of 32 sites with two sub-sweeps per MCS: the attempt loop that
+    # updates a slot's two halves as two cells, in small rings packed several
+    # per workgroup, a ragged ring, and windows (several launches)
+    kw = dict(dict(cell_log2=5, subsweeps=2, seed=21, stream=6), **rates, **shape)
+    sim = A.Simulation(A.make_params(samples=1, **kw))
+    loop = sim.plan()["attempt_loop"]
+    sim.close()
+    assert loop == (B.ASEP_LOOP_H6B0 if rates["q"] == 0 else B.ASEP_LOOP_H5B1)
+    compare(orc, kw, [0, 1, 7, 130, 300], 3)
+
+
+@pytest.mark.parametrize("lane_rate", [0.5, 0.1, 1.0])
+def test_two_lane_many_lane_changes(orc, lane_rate):
+    # every site a turning point, half filled lanes: most cells meet more
+    # than four lane-change candidates per sub-sweep, the case the fast loop
+    # hands to its exact replay; lane_rate 1 changes lanes without a draw
+    kw = dict(L=4096, model=1, init=1, density=0.5, p=1.0, q=1.0, lane_rate=lane_rate,
+              turn_frac=1.0, seed=5, stream=9)
+    compare(orc, kw, [0, 1, 4, 9], 3)
+
+
 def test_two_lane_general_rates(orc):
     kw = dict(L=512, model=1, init=1, density=0.5, p=0.7, q=0.4, lane_rate=0.1,
               turn_frac=0.2, seed=2, stream=8)

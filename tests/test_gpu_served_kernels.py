@@ -54,6 +54,9 @@ RING_CASES = [
     (dict(p=0.75, q=0.25, slow_frac=0.3, slow_factor=0.5, init=1),
      B.ASEP_LOOP_GENERIC, 1),                                                   # 3 bits: 3 per draw
     (dict(p=0.9, q=0.3, cell_log2=5, subsweeps=2, init=1), B.ASEP_LOOP_GENERIC, 1),
+    # cells of 32 sites, two sub-sweeps: a slot's halves are two cells
+    (dict(p=1.0, q=0.0, cell_log2=5, subsweeps=2), B.ASEP_LOOP_H6B0, 0),
+    (dict(p=0.5, q=0.5, cell_log2=5, subsweeps=2, init=1, density=0.45), B.ASEP_LOOP_H5B1, 1),
 ]
 
 # ring size -> slots per lane of a whole single-lane ring
@@ -91,8 +94,13 @@ def test_sixteen_slots_disorder_both_directions(orc, pool):
 
 
 LANE_CASES = [
+    # hop rates 0 or 1: four fields per draw, no compared bit; lane changes
+    # always accepted (no draw), or drawn at 32 bits (the two-lane workload),
+    # or so frequent that most cells meet a fifth candidate (exact replay)
     (dict(p=1.0, q=1.0, lane_rate=1.0, turn_frac=0.05), B.ASEP_LOOP_F4B0_LANES),
-    (dict(p=1.0, q=1.0, lane_rate=0.1, turn_frac=0.05), B.ASEP_LOOP_F1),    # 24 compared bits
+    (dict(p=1.0, q=1.0, lane_rate=0.1, turn_frac=0.05), B.ASEP_LOOP_F4B0_LANES),
+    (dict(p=1.0, q=1.0, lane_rate=0.5, turn_frac=1.0, density=0.5), B.ASEP_LOOP_F4B0_LANES),
+    (dict(p=0.1, q=0.9, lane_rate=0.1, turn_frac=0.05), B.ASEP_LOOP_F1),    # 24 compared hop bits
     (dict(p=0.5, q=0.5, lane_rate=0.5, turn_frac=0.2), B.ASEP_LOOP_GENERIC),  # 3 per draw
 ]
 
@@ -100,7 +108,7 @@ LANE_CASES = [
 @pytest.mark.parametrize("L,C", [(1 << 17, 4), (1 << 18, 8)], ids=["L2p17", "L2p18"])
 @pytest.mark.parametrize("rates,loop", LANE_CASES, ids=_ids([(c[0], c[1]) for c in LANE_CASES]))
 def test_two_lane_whole_rings(orc, pool, L, C, rates, loop):
-    kw = dict(L=L, model=1, init=1, density=0.3, seed=4, stream=20 + C, windows=1, **rates)
+    kw = dict(dict(L=L, model=1, init=1, density=0.3, seed=4, stream=20 + C, windows=1), **rates)
     plan = dict(windows=1, slots_per_lane=C, attempt_loop=loop)
     compare(orc, A, kw, [0, 1, 3], 2, plan=plan, pool=pool)
     sweep_and_compare_states(orc, A, kw, 2, 1, plan=plan)

@@ -340,7 +340,8 @@ def test_two_lane_law_exact(orc):
                    q=0.25, lane_rate=0.25, turn_frac=0.5, cell_log2=1, subsweeps=S,
                    samples_per_disorder=n)
     s = orc.lower(P)
-    pa, pb, om = (s["T"][i] / 2 ** s["b"] for i in range(3))
+    pa, pb = (s["T"][i] / 2 ** s["b"] for i in range(2))
+    om = s["T"][2] / 2 ** s["bc"]
     _, _, turn = orc.init_masks(P, 0)
     tl = me.TwoLane(L, pa, pb, om, turn)
     counts = {}
@@ -409,11 +410,11 @@ def test_ew_saturation_width(orc):
     assert abs(vals.mean() - (L + 1) / 12) < 5 * vals.std() / np.sqrt(len(vals)) + 0.05
 
 
-def _growth_slope(orc, p, q, L=8192, t_hi=3000, n=16):
+def _growth_slope(orc, p, q, L=8192, t_hi=3000, n=16, cell_log2=6, subsweeps=4):
     from concurrent.futures import ThreadPoolExecutor
 
     times = orc.sample_times(30, 1.05, t_hi)
-    P = orc.Params(L=L, p=p, q=q)
+    P = orc.Params(L=L, p=p, q=q, cell_log2=cell_log2, subsweeps=subsweeps)
     with ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
         W = list(ex.map(lambda smp: orc.run(P, smp, times).w2(L), range(n)))
     W = np.mean(W, axis=0) - 0.25  # subtract the intrinsic width (Sec. 2.2)
@@ -422,22 +423,32 @@ def _growth_slope(orc, p, q, L=8192, t_hi=3000, n=16):
     return np.polyfit(np.log(t[sel]), np.log(W[1:][sel]), 1)[0]
 
 
-def test_growth_exponent_kpz(orc):
+# cells of 64 sites with four sub-sweeps per MCS, and of 32 sites with two
+SCHEDULES = [(6, 4), (5, 2)]
+
+
+@pytest.mark.parametrize("cell_log2,subsweeps", SCHEDULES)
+def test_growth_exponent_kpz(orc, cell_log2, subsweeps):
     f = _gold("paper_facts.json")["kpz_exponents"]
     two_beta = 2 * f["alpha"] / f["z"]
-    assert abs(_growth_slope(orc, 1.0, 0.0) - two_beta) < 0.05
+    slope = _growth_slope(orc, 1.0, 0.0, cell_log2=cell_log2, subsweeps=subsweeps)
+    assert abs(slope - two_beta) < 0.05
 
 
-def test_growth_exponent_ew(orc):
+@pytest.mark.parametrize("cell_log2,subsweeps", SCHEDULES)
+def test_growth_exponent_ew(orc, cell_log2, subsweeps):
     # 1+1 dimensional Edwards-Wilkinson: beta = 1/4
-    assert abs(_growth_slope(orc, 0.5, 0.5) - 0.5) < 0.05
+    slope = _growth_slope(orc, 0.5, 0.5, cell_log2=cell_log2, subsweeps=subsweeps)
+    assert abs(slope - 0.5) < 0.05
 
 
-def test_schedule_matches_random_sequential(orc):
+@pytest.mark.parametrize("cell_log2,subsweeps", SCHEDULES)
+def test_schedule_matches_random_sequential(orc, cell_log2, subsweeps):
     # W^2(t) of the shifted decomposition and of random-sequential updates agree
     # within error bars once time is rescaled by the bond-attempt rate 1 - 1/ell
     L, n = 1024, 48
-    P = orc.Params(L=L, p=1.0, q=0.0, subsweeps=4)
+    ell = 1 << cell_log2
+    P = orc.Params(L=L, p=1.0, q=0.0, cell_log2=cell_log2, subsweeps=subsweeps)
     ts = [64, 128, 256, 512]
     dd, rs = [], []
     for smp in range(n):
@@ -445,7 +456,7 @@ def test_schedule_matches_random_sequential(orc):
         st = orc.init_state(P, smp)
         prev, w = 0, []
         for t in ts:
-            tr = t * 63 // 64
+            tr = t * (ell - 1) // ell
             orc.rsu(P, smp, st, prev, tr - prev)
             prev = tr
             S1, S2, _ = orc.sums(st, L)
