@@ -444,7 +444,10 @@ static bool plan_windows(const Resolved& r, uint32_t segs, uint32_t K, Plan* p) 
     const uint32_t nw = r.nw;
     if (segs < 2 || segs > nw) return false;
     const uint32_t seg_n = (nw + segs - 1) / segs;
-    if ((uint64_t)(segs - 1) * seg_n >= nw) return false;  // every window owns words
+    // windows of seg_n words: as many as it takes (every window owns words;
+    // a count whose last window would be empty becomes the next smaller one)
+    segs = (nw + seg_n - 1) / seg_n;
+    if (segs < 2) return false;
     // the window starts exactly its drift (at most K+1 words) before its
     // output and reaches K+1 words past it (the garbage depth)
     const uint32_t halo = K + 1;
@@ -490,22 +493,25 @@ static int choose_plan(const Resolved& r, Plan* p) {
     Plan whole;
     const bool have_whole = plan_whole(r, &whole);
     const uint32_t R = r.P.samples;
-    if (have_whole) {
-        // windows only pay when whole rings would leave compute units idle and
-        // the rings are long enough for the halo to stay small
-        if (whole.grid >= ncu || r.nw < 16 * (K + 1)) {
-            *p = whole;
-            return ASEP_OK;
-        }
-        const uint32_t segs = (ncu + R - 1) / R;
-        if (segs >= 2 && r.nw / segs >= 8 * (K + 1) && plan_windows(r, segs, K, p)) return ASEP_OK;
+    // Whole rings when they fill the compute units or are too short for
+    // windows.  Otherwise windows: as many as it takes to give each compute
+    // unit a workgroup, but no more than keep every window's output at least
+    // twice its reach (K + 1 words), and at least as many as fit a workgroup
+    // -- a few long rings in a few workgroups would hold a handful of CUs
+    // for the whole run (and a served request's launch shares the GPU with
+    // at most three others, one per hardware queue).
+    if (have_whole && (whole.grid >= ncu || r.nw < 4 * (K + 1))) {
         *p = whole;
         return ASEP_OK;
     }
-    // rings too long for one workgroup: smallest window count that fits
-    for (uint32_t segs = 2; segs <= r.nw; segs = segs + (segs >> 2) + 1) {
-        uint32_t s2 = std::max(segs, (ncu + R - 1) / R);
-        if (plan_windows(r, s2, K, p)) return ASEP_OK;
+    const uint32_t fill = (ncu + R - 1) / R;
+    const uint32_t cap = std::max(2u, r.nw / (2 * (K + 1)));
+    for (uint32_t segs = std::max(2u, std::min(fill, cap)); segs <= r.nw;
+         segs = segs + (segs >> 2) + 1)
+        if (plan_windows(r, segs, K, p)) return ASEP_OK;
+    if (have_whole) {
+        *p = whole;
+        return ASEP_OK;
     }
     return ASEP_E_UNSUPPORTED;
 }
@@ -520,6 +526,7 @@ struct asep_sim {
     uint64_t* masks = nullptr;
     int64_t* hops = nullptr;
     Record* rec = nullptr;      // device staging
+    SegRec* segs = nullptr;     // measurement segments
     uint32_t rec_cap = 0;       // records per ring the staging holds
     void* own_state = nullptr;
     void* own_aux = nullptr;
@@ -571,7 +578,16 @@ static void aux_layout(const Resolved& r, const Plan& pl, size_t* o_masks, size_
     off = (off + 255) & ~(size_t)255;
     *o_alt = off;
     if (pl.seg) off += (size_t)r.P.samples * r.planes * r.nw * 8;
+    off = (off + 255) & ~(size_t)255;
+    off += rough_seg_bytes(r.P.samples, r.nw);  // measurement segments (last)
     *total = (off + 255) & ~(size_t)255;
+}
+
+// Offset of the measurement segments: after the second state buffer.
+static size_t seg_offset(const Resolved& r, const Plan& pl, size_t o_alt) {
+    size_t off = o_alt;
+    if (pl.seg) off += (size_t)r.P.samples * r.planes * r.nw * 8;
+    return (off + 255) & ~(size_t)255;
 }
 
 static int buffer_sizes_on(const asep_params* p, int dev, size_t* state_bytes,
@@ -658,6 +674,7 @@ static int create_common(const asep_params* p, void* state, size_t state_bytes, 
         s->own_host_rec = true;
     }
     s->alt = s->plan.seg ? (uint64_t*)(a + o_alt) : nullptr;
+    s->segs = (SegRec*)(a + seg_offset(s->r, s->plan, o_alt));
     s->rec_cap = kRecCap;
     rc = sim_init(s);
     if (rc) {
@@ -842,7 +859,7 @@ static int enqueue_to(asep_sim* s, uint64_t t_end, const uint64_t* times, uint32
         for (;;) {
             while (ri < n && times[ri] * S == g) {
                 HIP_OR_FAIL(launch_rough(cur, s->hops, s->rec + (size_t)ri * r.P.samples,
-                                         r.P.samples, r.planes, r.nw, s->stream));
+                                         r.P.samples, r.planes, r.nw, s->segs, s->stream));
                 ++ri;
             }
             if (g >= g_end) break;
@@ -926,7 +943,8 @@ static void fill_rough(const Resolved& r, const Record& rc, asep_rough* o) {
 extern "C" int asep_roughness(asep_sim* s, asep_rough* out) {
     if (!s || !out) return ASEP_E_INVAL;
     const Resolved& r = s->r;
-    HIP_OR_FAIL(launch_rough(s->words, s->hops, s->rec, r.P.samples, r.planes, r.nw, s->stream));
+    HIP_OR_FAIL(launch_rough(s->words, s->hops, s->rec, r.P.samples, r.planes, r.nw, s->segs,
+                             s->stream));
     HIP_OR_FAIL(hipMemcpyAsync(s->host_rec, s->rec, sizeof(Record) * r.P.samples,
                                hipMemcpyDeviceToHost, s->stream));
     HIP_OR_FAIL(hipStreamSynchronize(s->stream));
@@ -1087,6 +1105,7 @@ int sim_run_scratch(const asep_params* p, uint64_t* state, size_t state_bytes, h
     s.hops = (int64_t*)(a + o_hops);
     s.rec = (Record*)(a + o_rec);
     s.alt = s.plan.seg ? (uint64_t*)(a + o_alt) : nullptr;
+    s.segs = (SegRec*)(a + seg_offset(s.r, s.plan, o_alt));
     s.rec_cap = kRecCap;
     rc = check_times(&s, times, n);
     if (rc) return rc;

@@ -28,6 +28,30 @@ struct Record {
     int64_t n;
 };
 
+// Measurement of rings held in HBM: each ring is cut into segments of
+// `seg` words, each summed by one wave relative to its own start height
+// (d = height change, s1 and s2 = sums of heights and squared heights,
+// n = particles), then combined per ring in exact 128-bit arithmetic.
+struct SegRec {
+    int64_t d;
+    int64_t s1;
+    uint64_t s2;
+    int64_t n;
+};
+
+// Segment length in words: a power of two from 128 to 16384, the smallest
+// that keeps the segments of all rings at most 4096 (enough waves to keep
+// HBM busy, few enough for the per-ring combine).
+inline uint32_t rough_seg_words(uint32_t R, uint32_t nw) {
+    uint32_t seg = 128;
+    while (seg < 16384 && (uint64_t)R * ((nw + seg - 1) / seg) > 4096) seg <<= 1;
+    return seg;
+}
+inline size_t rough_seg_bytes(uint32_t R, uint32_t nw) {
+    const uint32_t seg = rough_seg_words(R, nw);
+    return sizeof(SegRec) * (size_t)R * ((nw + seg - 1) / seg);
+}
+
 // The lowered update rule: cell size, sub-sweeps, draw packing, thresholds.
 struct Sched {
     uint32_t lam;   // log2 of the cell size ell
@@ -78,7 +102,7 @@ hipError_t launch_init_masks(uint64_t* masks, uint32_t n_real, uint32_t mplanes,
                              const uint32_t* tags, uint32_t nw, uint64_t T, uint32_t key0,
                              uint32_t key1, uint32_t real0, hipStream_t st);
 hipError_t launch_rough(const uint64_t* words, const int64_t* hops, Record* rec, uint32_t R,
-                        uint32_t planes, uint32_t nw, hipStream_t st);
+                        uint32_t planes, uint32_t nw, SegRec* segs, hipStream_t st);
 // words[0 .. n) = 0 (a kernel, not a memset node).
 hipError_t launch_zero_u64(uint64_t* words, uint64_t n, hipStream_t st);
 

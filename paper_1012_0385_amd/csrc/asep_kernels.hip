@@ -37,7 +37,6 @@ namespace {
 using dev::Blk;
 using dev::build_byte_tables;
 using dev::philox;
-using dev::word_moments;
 
 // Word of 64 per-site Bernoulli draws: site 64w+i uses word i%4 of the block
 // at counter (16w + i/4, c1, tag << 28, c3).
@@ -85,65 +84,155 @@ __global__ void k_init_masks(uint64_t* __restrict__ masks, uint32_t n_real, uint
     }
 }
 
-// Measurement of rings resident in HBM: one workgroup per ring.  Each lane
-// takes a contiguous run of words; an exclusive scan of the per-word height
-// steps 64 - 2 popcount gives the height at every word start, then the byte
-// tables give the in-word sums.  S2 is accumulated in 128 bits.
-__global__ __launch_bounds__(256) void k_rough(const uint64_t* __restrict__ words,
-                                               const int64_t* __restrict__ hops,
-                                               Record* __restrict__ rec, uint32_t planes,
-                                               uint32_t nw) {
-    __shared__ int32_t tab1[256], tab2[256];
-    __shared__ int64_t sc[256];
-    __shared__ unsigned long long rlo[256], rhi[256];
-    __shared__ long long rs1[256], rn[256];
-    const uint32_t ring = blockIdx.x;
-    const uint32_t tid = threadIdx.x;
-    build_byte_tables(tab1, tab2);
-    const uint64_t* wa = words + (size_t)ring * planes * nw;
-    const uint32_t per = (nw + blockDim.x - 1) / blockDim.x;
-    const uint32_t w0 = min(nw, tid * per), w1 = min(nw, w0 + per);
-    int64_t dsum = 0, n = 0;
-    for (uint32_t w = w0; w < w1; ++w) {
-        const uint64_t x = wa[w];
-        dsum += 64 - 2 * (int64_t)__popcll(x);
-        n += __popcll(x);
-        if (planes > 1) n += __popcll(wa[nw + w]);
+// Sums of heights inside one word relative to the height at its first site
+// (as word_moments), in 32-bit arithmetic: |d| <= 64, |e1| <= 2016,
+// e2 <= 64^3.
+__device__ __forceinline__ void word_moments32(uint64_t word, const int32_t* tab1,
+                                               const int32_t* tab2, int32_t& e1, int32_t& e2) {
+    int32_t d = 0;
+    e1 = 0;
+    e2 = 0;
+#pragma unroll
+    for (int by = 0; by < 8; ++by) {
+        const uint32_t byte = (uint32_t)(word >> (8 * by)) & 255u;
+        const int32_t t1 = tab1[byte];
+        e1 += 8 * d + t1;
+        e2 += 8 * d * d + 2 * d * t1 + tab2[byte];
+        d += 8 - 2 * __popc(byte);
     }
+}
+
+// Measurement of rings held in HBM, pass 1: one wave per segment of `seg`
+// words (segment s of ring r is words [s seg, (s+1) seg) of the ring).  The
+// wave walks its segment in slabs of 128 words, each lane loading two
+// consecutive words with one 16-byte load (coalesced), a wave scan of the
+// per-word height steps 64 - 2 popcount giving each word's start height;
+// the byte tables give the in-word sums.  Heights are relative to the
+// segment's start, so a segment's S2 stays below 2^60 (2^20 sites of height
+// below 2^20).
+__global__ __launch_bounds__(256) void k_rough_seg(const uint64_t* __restrict__ words,
+                                                   uint32_t planes, uint32_t nw, uint32_t seg,
+                                                   uint32_t nseg, uint32_t total,
+                                                   SegRec* __restrict__ out) {
+    __shared__ int32_t tab1[256], tab2[256];
+    build_byte_tables(tab1, tab2);
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t gs = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (gs >= total) return;  // whole waves; no barrier follows
+    const uint32_t ring = gs / nseg, sg = gs - ring * nseg;
+    const uint32_t w0 = sg * seg, w1 = min(nw, w0 + seg);
+    const uint64_t* wa = words + (size_t)ring * planes * nw;
+    int32_t carry = 0;
+    int64_t s1 = 0, n = 0;
+    uint64_t s2 = 0;
+    for (uint32_t b = w0; b < w1; b += 128) {
+        const uint32_t i0 = b + 2u * lane;
+        const bool v0 = i0 < w1, v1 = i0 + 1 < w1;
+        uint64_t x0 = 0, x1 = 0;
+        if (v1 && ((((size_t)ring * planes * nw + i0) & 1u) == 0)) {
+            const ulonglong2 q = *reinterpret_cast<const ulonglong2*>(wa + i0);
+            x0 = q.x;
+            x1 = q.y;
+        } else {
+            if (v0) x0 = wa[i0];
+            if (v1) x1 = wa[i0 + 1];
+        }
+        n += __popcll(x0) + __popcll(x1);
+        if (planes > 1) {
+            if (v0) n += __popcll(wa[nw + i0]);
+            if (v1) n += __popcll(wa[nw + i0 + 1]);
+        }
+        const int32_t d0 = v0 ? 64 - 2 * (int32_t)__popcll(x0) : 0;
+        const int32_t d1 = v1 ? 64 - 2 * (int32_t)__popcll(x1) : 0;
+        // inclusive wave scan of the lane's two steps
+        const int32_t t = d0 + d1;
+        int32_t inc = t;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int32_t y = __shfl_up(inc, o, 64);
+            if ((int)lane >= o) inc += y;
+        }
+        const int32_t h0 = carry + inc - t, h1 = h0 + d0;
+        int32_t e1, e2;
+        if (v0) {
+            word_moments32(x0, tab1, tab2, e1, e2);
+            s1 += 64 * (int64_t)h0 + e1;
+            s2 += (uint64_t)(64 * (int64_t)h0 * h0 + 2 * (int64_t)h0 * e1 + e2);
+        }
+        if (v1) {
+            word_moments32(x1, tab1, tab2, e1, e2);
+            s1 += 64 * (int64_t)h1 + e1;
+            s2 += (uint64_t)(64 * (int64_t)h1 * h1 + 2 * (int64_t)h1 * e1 + e2);
+        }
+        carry += __shfl(inc, 63, 64);
+    }
+    // wave sums (every lane ends with the totals)
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        s1 += (int64_t)__shfl_xor((long long)s1, o, 64);
+        s2 += (uint64_t)__shfl_xor((unsigned long long)s2, o, 64);
+        n += (int64_t)__shfl_xor((long long)n, o, 64);
+    }
+    if (lane == 0) {
+        SegRec r;
+        r.d = carry;
+        r.s1 = s1;
+        r.s2 = s2;
+        r.n = n;
+        out[gs] = r;
+    }
+}
+
+// Pass 2, one workgroup per ring: segment start heights from an exclusive
+// scan of the segments' height changes, then the exact ring sums
+//   S1 = sum (s1 + M H),  S2 = sum (s2 + 2 H s1 + M H^2)
+// (M sites in a segment starting at height H), S2 in 128 bits.
+__global__ __launch_bounds__(256) void k_rough_combine(const SegRec* __restrict__ segs,
+                                                       uint32_t nseg, uint32_t seg, uint32_t nw,
+                                                       const int64_t* __restrict__ hops,
+                                                       Record* __restrict__ rec) {
+    __shared__ int64_t sc[256];
+    __shared__ unsigned long long rlo[256];
+    __shared__ long long rhi[256], rs1[256], rn[256];
+    const uint32_t ring = blockIdx.x, tid = threadIdx.x;
+    const SegRec* sr = segs + (size_t)ring * nseg;
+    const uint32_t per = (nseg + blockDim.x - 1) / blockDim.x;
+    const uint32_t a = min(nseg, tid * per), z = min(nseg, a + per);
+    int64_t dsum = 0;
+    for (uint32_t i = a; i < z; ++i) dsum += sr[i].d;
     sc[tid] = dsum;
     __syncthreads();
-    for (uint32_t d = 1; d < blockDim.x; d <<= 1) {
-        const int64_t v = sc[tid] + (tid >= d ? sc[tid - d] : 0);
+    for (uint32_t o = 1; o < blockDim.x; o <<= 1) {
+        const int64_t v = sc[tid] + (tid >= o ? sc[tid - o] : 0);
         __syncthreads();
         sc[tid] = v;
         __syncthreads();
     }
     int64_t H = sc[tid] - dsum;
-    int64_t s1 = 0;
-    unsigned long long lo = 0, hi = 0;
-    for (uint32_t w = w0; w < w1; ++w) {
-        const uint64_t x = wa[w];
-        int64_t e1, e2;
-        word_moments(x, tab1, tab2, e1, e2);
-        s1 += 64 * H + e1;
-        const uint64_t add = (uint64_t)(64 * H * H + 2 * H * e1 + e2);
-        lo += add;
-        hi += (lo < add) ? 1u : 0u;
-        H += 64 - 2 * (int64_t)__popcll(x);
+    __int128 S2 = 0;
+    int64_t S1 = 0, N = 0;
+    for (uint32_t i = a; i < z; ++i) {
+        const SegRec r = sr[i];
+        const int64_t M = 64 * (int64_t)(min(nw, (i + 1) * seg) - i * seg);
+        S1 += r.s1 + M * H;
+        S2 += (__int128)r.s2 + 2 * (__int128)H * r.s1 + (__int128)M * H * H;
+        N += r.n;
+        H += r.d;
     }
-    rlo[tid] = lo;
-    rhi[tid] = hi;
-    rs1[tid] = s1;
-    rn[tid] = n;
+    rlo[tid] = (unsigned long long)(uint64_t)S2;
+    rhi[tid] = (long long)(int64_t)(S2 >> 64);
+    rs1[tid] = S1;
+    rn[tid] = N;
     __syncthreads();
-    for (uint32_t d = blockDim.x / 2; d > 0; d >>= 1) {
-        if (tid < d) {
-            const unsigned long long a = rlo[tid], b = rlo[tid + d];
-            const unsigned long long s = a + b;
-            rlo[tid] = s;
-            rhi[tid] = rhi[tid] + rhi[tid + d] + (s < a ? 1u : 0u);
-            rs1[tid] += rs1[tid + d];
-            rn[tid] += rn[tid + d];
+    for (uint32_t o = blockDim.x / 2; o > 0; o >>= 1) {
+        if (tid < o) {
+            const unsigned long long x = rlo[tid], y = rlo[tid + o];
+            const unsigned long long t = x + y;
+            rlo[tid] = t;
+            rhi[tid] = rhi[tid] + rhi[tid + o] + (t < x ? 1 : 0);
+            rs1[tid] += rs1[tid + o];
+            rn[tid] += rn[tid + o];
         }
         __syncthreads();
     }
@@ -151,7 +240,7 @@ __global__ __launch_bounds__(256) void k_rough(const uint64_t* __restrict__ word
         Record r;
         r.s1 = rs1[0];
         r.s2lo = rlo[0];
-        r.s2hi = (int64_t)rhi[0];
+        r.s2hi = rhi[0];
         r.hops = hops[ring];
         r.n = rn[0];
         rec[ring] = r;
@@ -231,9 +320,15 @@ hipError_t launch_sweep(const SweepKernel& k, const SimDesc& one, const SimDesc*
 }
 
 hipError_t launch_rough(const uint64_t* words, const int64_t* hops, Record* rec, uint32_t R,
-                        uint32_t planes, uint32_t nw, hipStream_t st) {
+                        uint32_t planes, uint32_t nw, SegRec* segs, hipStream_t st) {
+    const uint32_t seg = rough_seg_words(R, nw);
+    const uint32_t nseg = (nw + seg - 1) / seg;
+    const uint32_t total = R * nseg;
     (void)hipGetLastError();
-    hipLaunchKernelGGL(k_rough, dim3(R), dim3(256), 0, st, words, hops, rec, planes, nw);
+    hipLaunchKernelGGL(k_rough_seg, dim3((total + 3) / 4), dim3(256), 0, st, words, planes, nw,
+                       seg, nseg, total, segs);
+    hipLaunchKernelGGL(k_rough_combine, dim3(R), dim3(256), 0, st, segs, nseg, seg, nw, hops,
+                       rec);
     return hipGetLastError();
 }
 

@@ -2,7 +2,7 @@
 
     python -m paper_1012_0385_amd.run_workload NAME [--mcs N] [--start T]
 
-Runs the workload's ensemble at its tuned launch shape from MCS T (default:
+Runs the workload's ensemble at its tuned launch shape and cell schedule from MCS T (default:
 the middle of the job, the clock set with asep_set_time) for N MCS with the
 job's own measurement times in that span, after a short warm-up, and prints
 one JSON line with the rate.  NAME is a key of workloads.WORKLOADS.
@@ -31,7 +31,8 @@ def main() -> None:
     start = t_max // 2 if args.start < 0 else args.start
     full = times if times is not None else W.geometric_times(t_max)
     span = [start] + [t for t in full if start < t < start + args.mcs] + [start + args.mcs]
-    sim = A.Simulation(A.make_params(samples=samples, **kw, **tune.lookup(kw, samples)))
+    A.load_tuning(tune.DEFAULT_TABLE)  # launch shape and cell schedule from the table
+    sim = A.Simulation(A.make_params(samples=samples, **kw))
     sim.run([0, 1])  # warm-up
     sim.reset()
     sim.set_time(start)

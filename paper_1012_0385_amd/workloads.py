@@ -39,6 +39,9 @@ WORKLOADS = {
                              stream=5, schedule=1), 120, 10 ** 6, None,
                         "Q-SSEP (Q = 0.5, r = 0.2, p = q = 0.5), 120 realisations of 2^15, "
                         "two-sub-lattice update, 10^6 MCS"),
+    "hbm_L2p26": (dict(L=1 << 26, p=1.0, q=0.0, seed=1, stream=7), 64, 1000, None,
+                  "64 KPZ rings of 2^26 sites (512 MiB of state, beyond the 256 MB "
+                  "last-level cache: resident in HBM), 1000 MCS"),
     "two_lane_sca_L2p12": (dict(L=1 << 12, model=1, init=1, density=0.5, p=0.5, q=0.5,
                                 lane_rate=0.8, slow_frac=0.5, slow_factor=0.25, seed=1, stream=6,
                                 schedule=1), 1024, 10 ** 5, None,

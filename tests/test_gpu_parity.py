@@ -168,6 +168,29 @@ def test_half_word_cells(orc, rates, shape):
     compare(orc, kw, [0, 1, 7, 130, 300], 3)
 
 
+@pytest.mark.parametrize("kw,samples", [
+    (dict(L=64 * 67, model=1, init=1, density=0.3, p=1.0, q=1.0, lane_rate=0.1,
+          turn_frac=0.05), 3),                                   # odd word count, two planes
+    (dict(L=64 * 33331, init=1, density=0.45, p=0.5, q=0.5), 2),  # many segments per ring
+    (dict(L=4096, init=1, density=0.5), 70),                      # one segment per ring
+], ids=["two-lane-odd", "long-odd", "many-rings"])
+def test_roughness_of_any_layout(orc, kw, samples):
+    # the measurement of rings in HBM (segments summed per wave, combined per
+    # ring in 128 bits) against the oracle's sums of the words read back
+    sim = A.Simulation(A.make_params(samples=samples, seed=4, stream=2, **kw))
+    sim.sweep(3)
+    r = sim.roughness()
+    L = kw["L"]
+    for i in range(samples):
+        st = orc.unpack_words(sim.read_state(i))
+        S1, S2, N = orc.sums(st, L)
+        if kw.get("model", 0) == 1:
+            N += int(st[L:].sum())
+        assert (r.S1[i], r.S2[i], r.N[i]) == (S1, S2, N), i
+        assert abs(r.w2[i] - orc.w2(L, S1, S2)) <= 1e-12 * orc.w2(L, S1, S2)
+    sim.close()
+
+
 @pytest.mark.parametrize("lane_rate", [0.5, 0.1, 1.0])
 def test_two_lane_many_lane_changes(orc, lane_rate):
     # every site a turning point, half filled lanes: most cells meet more
@@ -378,26 +401,32 @@ def _site_bits(words):
 
 def test_benchmark_configuration(orc):
     # the benchmark exactly: 64 KPZ and 64 EW rings of 2^17 sites from the flat
-    # start, at the tuned launch shape, both ensembles advanced together; sampled
-    # rings against the oracle, every ring against the conservation law and the
-    # hop-count identity (J = change of the position sum modulo L)
+    # start, at the tuned launch shape and cell schedule of the shipped table,
+    # both ensembles advanced together; sampled rings against the oracle (with
+    # the schedule the library resolved), every ring against the conservation
+    # law and the hop-count identity (J = change of the position sum modulo L)
     from concurrent.futures import ThreadPoolExecutor
 
     from paper_1012_0385_amd import tune
+    from parity_util import oracle_params_from
 
     L, R, times = 1 << 17, 64, [0, 1, 8, 64, 200]
     kws = [dict(L=L, p=1.0, q=0.0, seed=1, stream=0), dict(L=L, p=0.5, q=0.5, seed=1, stream=1)]
     sims = []
-    for kw in kws:
-        shape = tune.lookup(kw, R)
-        print("case: benchmark ensemble", kw, shape, flush=True)
-        sims.append(A.Simulation(A.make_params(samples=R, **kw, **shape), stream=torch.cuda.Stream()))
+    try:
+        A.load_tuning(tune.DEFAULT_TABLE)
+        for kw in kws:
+            sims.append(A.Simulation(A.make_params(samples=R, **kw), stream=torch.cuda.Stream()))
+            print("case: benchmark ensemble", kw, sims[-1].plan(), "cell", 1 << sims[-1].params.cell_log2,
+                  "S", sims[-1].params.subsweeps, flush=True)
+    finally:
+        A.load_tuning(None)
     got = A.run_batch(sims, times)
     pos = np.arange(L, dtype=np.int64)
     P0 = int(pos[::2].sum())
     picks = (0, 37, R - 1)
     with ThreadPoolExecutor(6) as ex:
-        refs = {(m, i): ex.submit(orc.run, oracle_params(orc, kw), i, times)
+        refs = {(m, i): ex.submit(orc.run, oracle_params_from(orc, sims[m].params), i, times)
                 for m, kw in enumerate(kws) for i in picks}
         for m, (kw, sim, g) in enumerate(zip(kws, sims, got)):
             for i in range(R):
