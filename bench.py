@@ -55,10 +55,10 @@ UPDATE_SLOTS = 6
 # only for the kernel sources they were taken on (SHA-256 prefix below) and
 # for that launch shape; otherwise the bench reports traffic as unknown.
 SWEEP_TRAFFIC = {
-    "src_sha256": "6ccf0d3e687eaae0",
-    "launch_shape": {"windows": 4, "window_sweeps": 255, "rings_per_wg": 0},
-    "fetch_kib": 840.48,   # KPZ 839.7, EW 841.25
-    "write_kib": 1032.0,
+    "src_sha256": "9cd9babb0961de85",
+    "launch_shape": {"windows": 3, "window_sweeps": 63, "rings_per_wg": 0},
+    "fetch_kib": 636.12,   # KPZ 633.12, EW 639.12
+    "write_kib": 1034.0,
     "fetch_scale": 2.0,    # 4 GiB copy: FETCH_SIZE 2097206 KiB
     "write_scale": 1.0,    # 4 GiB copy: WRITE_SIZE 4194304 KiB
 }
@@ -304,9 +304,22 @@ def cpu_baseline(times_all, n_rings, t_cut, full_ring=False, sched=(6, 4)):
                                       "to min(t_max, 2^28 / L) MCS; %.1f s wall" % dt}
     out["other_workloads"] = others
     if full_ring:
+        # the whole 10^5-MCS job of one ring on one core, advanced between
+        # its measurement times with a progress line every 10^4 MCS
         P = oracle.Params(L=L, p=1.0, q=0.0, seed=1, stream=0, cell_log2=sched[0],
                           subsweeps=sched[1])
-        d = one_core(P, 0, times_all)
+        t0 = time.perf_counter()
+        st = oracle.init_state(P, 0)
+        J, t, mark = 0, 0, 0
+        for tm in times_all:
+            J = oracle.advance(P, 0, st, t, tm - t, J)
+            oracle.sums(st, L)
+            t = tm
+            if t >= mark + 10000:
+                mark = t
+                print("oracle full ring: %d MCS, %.0f s" % (t, time.perf_counter() - t0),
+                      file=sys.stderr, flush=True)
+        d = time.perf_counter() - t0
         out["single_core"]["full_L2p17_ring"] = {
             "value": L * times_all[-1] / d, "seconds": d,
             "sample": "1 KPZ ring of L=2^17 over all %d MCS with its %d measurements"

@@ -148,12 +148,14 @@ typedef struct asep_rough {
 
 typedef struct asep_sim asep_sim;
 
-/* Size in bytes of the two device buffers a simulation needs:
+/* Size in bytes of the two device buffers a simulation needs (Sec. 2.1: the
+ * ring's sites, one bit each here; Sec. 2.3 and 3: the quenched planes):
  * state: samples x planes x L/64 words (uint64, bit b of word w = site 64w+b);
  * aux:   quenched planes, hop counters and record staging. */
 int asep_buffer_sizes(const asep_params* p, size_t* state_bytes, size_t* aux_bytes);
 
-/* Validate, lower probabilities to integer thresholds, allocate the device
+/* Sec. 2.1 (flat start, exchange probabilities), Sec. 2.3, Sec. 3:
+ * validate, lower probabilities to integer thresholds, allocate the device
  * buffers (library-owned) on the current HIP device, create a stream and
  * initialise the state and the quenched planes.  *out receives the handle;
  * p->cell_log2, p->subsweeps and p->rbits as used are readable through
@@ -210,20 +212,24 @@ int asep_get_plan(const asep_sim* s, asep_plan* out);
  * validation and error codes as asep_create. */
 int asep_resolve(const asep_params* p, asep_params* resolved, asep_plan* plan);
 
-/* Advance every sample by n_mcs Monte Carlo steps; asynchronous on the
+/* Sec. 2.1 (one MCS: every site updated once on average; here S sub-sweeps
+ * of the parallel update): advance every sample by n_mcs Monte Carlo steps; asynchronous on the
  * simulation's stream.  Splitting n_mcs into several calls gives bit-identical
  * results. */
 int asep_sweep(asep_sim* s, uint64_t n_mcs);
 
-/* Measure the current state: out[samples] (host array).  Synchronises. */
+/* Sec. 2.1, Eq. W: measure the current state (heights, their exact sums,
+ * W^2): out[samples] (host array).  Synchronises. */
 int asep_roughness(asep_sim* s, asep_rough* out);
 
-/* Advance through ascending absolute times (MCS, each >= asep_time()) and
+/* Sec. 2.2, Eq. (sampling): W^2 recorded at chosen times while the run
+ * advances.  Advance through ascending absolute times (MCS, each >= asep_time()) and
  * measure at each: out[n_times * samples] (host array, time-major).  Equal to
  * asep_sweep + asep_roughness at each time, bit for bit.  Synchronises. */
 int asep_run(asep_sim* s, const uint64_t* times, uint32_t n_times, asep_rough* out);
 
-/* asep_run for several simulations at once: every simulation advances
+/* Sec. 2.1 (independent realisations advanced together on the device):
+ * asep_run for several simulations at once: every simulation advances
  * through the same times, each on its own stream, their launches queued
  * before the call waits on any of them so that they overlap on the GPU.
  * outs[k] receives simulation k's n_times x samples records.  Each result
@@ -258,24 +264,28 @@ int asep_run_noalloc(const asep_params* p, uint64_t* state_dev, size_t state_byt
                      void* hip_stream, const uint64_t* times, uint32_t n_times,
                      asep_rough* out_dev);
 
-/* Copy one sample's state words (planes x L/64 uint64, lane A first) to or
+/* Sec. 2.1 (the ring's occupation numbers n_i): copy one sample's state words (planes x L/64 uint64, lane A first) to or
  * from host memory; n_words must equal planes x L/64.  Synchronises. */
 int asep_read_state(asep_sim* s, uint32_t sample, uint64_t* words, uint64_t n_words);
 int asep_write_state(asep_sim* s, uint32_t sample, const uint64_t* words, uint64_t n_words);
 
-/* Quenched plane `plane` (ring: 0 = slow-p, 1 = slow-q; two lanes: 0 = turning
+/* Sec. 2.3, Eq. (bimodal) slow sites; Sec. 3 turning points.
+ * Quenched plane `plane` (ring: 0 = slow-p, 1 = slow-q; two lanes: 0 = turning
  * points) of one realisation, L/64 words.  ASEP_E_INVAL if the model has none. */
 int asep_read_mask(asep_sim* s, uint32_t plane, uint32_t realization, uint64_t* words,
                    uint64_t n_words);
 
-/* Cumulative hop counters J of all samples (host array[samples]); synchronises. */
+/* Sec. 3 (the current, c = J/L): cumulative hop counters J of all samples
+ * (host array[samples]); synchronises. */
 int asep_current(asep_sim* s, int64_t* hops);
 
-/* Set the MCS clock and hop counters, e.g. after asep_write_state from a
+/* Sec. 2.1 (time in MCS): set the MCS clock and hop counters, e.g. after
+ * asep_write_state from a
  * checkpoint.  hops may be NULL (zeros). */
 int asep_set_time(asep_sim* s, uint64_t t, const int64_t* hops);
 
-/* Re-run the initialisation (state, quenched planes), set the clock and the
+/* Sec. 2.1 (flat start), Sec. 2.3 / 3 (quenched planes): re-run the
+ * initialisation (state, quenched planes), set the clock and the
  * hop counters to zero; no allocation.  Asynchronous on the stream. */
 int asep_reset(asep_sim* s);
 
@@ -291,7 +301,7 @@ typedef struct asep_profile_stats {
 int asep_profile_enable(asep_sim* s, int enable);
 int asep_profile_read(asep_sim* s, asep_profile_stats* out);
 
-/* MCS completed so far (0 for a NULL handle). */
+/* Sec. 2.1 (time in MCS): MCS completed so far (0 for a NULL handle). */
 uint64_t asep_time(const asep_sim* s);
 
 /* Free library-owned memory and the library-owned stream; borrowed buffers
@@ -301,11 +311,12 @@ uint64_t asep_time(const asep_sim* s);
  * borrowed buffers.  NULL is ignored. */
 void asep_destroy(asep_sim* s);
 
-/* Ensemble mean of W^2 over n records of one time: sum of the exact numerators
+/* Sec. 2.1, Eq. W averaged over samples: ensemble mean of W^2 over n records
+ * of one time: sum of the exact numerators
  * L S2 - S1^2 in 128-bit integers, one conversion, independent of order. */
 int asep_ensemble_w2(const asep_rough* r, uint32_t n, uint64_t L, double* w2_mean);
 
-/* Geometric sampling times of Eq. (sampling): 0, then ceil(t_i) for real
+/* Sec. 2.2, geometric sampling times of Eq. (sampling): 0, then ceil(t_i) for real
  * t_0 = t0, t_{i+1} = factor t_i while ceil(t_i) <= t_max, duplicates dropped.
  * Writes at most cap values; *n receives the count written. */
 int asep_sample_times(double t0, double factor, uint64_t t_max, uint64_t* out, uint32_t cap,

@@ -486,7 +486,10 @@ static int choose_plan(const Resolved& r, Plan* p) {
     uint32_t ncu;
     device_limits(r.dev, &lim, &ncu);
     const uint32_t want = r.P.windows;  // windows per ring (0 = auto)
-    uint32_t K = r.P.window_sweeps ? r.P.window_sweeps : 63;  // sub-sweeps per window launch
+    // sub-sweeps per window launch: given, else 63 (longer launches need
+    // longer windows, i.e. fewer of them per ring: on the served mix that
+    // parallelism was worth more than the launches saved)
+    const uint32_t K = r.P.window_sweeps ? r.P.window_sweeps : 63;
     if (K > 4096) return ASEP_E_INVAL;
     if (want == 1) return plan_whole(r, p) ? ASEP_OK : ASEP_E_UNSUPPORTED;
     if (want >= 2) return plan_windows(r, want, K, p) ? ASEP_OK : ASEP_E_UNSUPPORTED;
