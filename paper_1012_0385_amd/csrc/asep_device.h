@@ -316,23 +316,31 @@ __device__ __forceinline__ int32_t cell_ring_fast(uint64_t& x, uint64_t m0, uint
 // 32-bit word, BB (<= 2) compared bits; the outcome is one bit of lutP
 // indexed by the pair and the compared bits, and the arithmetic shift makes
 // j = 31 (the bond leaving the cell) a no-op, as in cell_ring_fast.
-template <int A, int BB, bool Q0, int NA>
-__device__ __forceinline__ int32_t cell_half_fast(uint64_t& x, const CellCtx& c) {
-    constexpr int PER = 4 * A;
-    constexpr int NB = (NA + PER - 1) / PER;
+// With columnar disorder (DIS) the forward mark at j, and with backward hops
+// the backward mark at j + 1, join the pair and the compared bits in the
+// offset of lutD, as in cell_ring_fast; the marks come from the same half of
+// the slot's mark words.
+// The draws of the two cells are the first Philox block of cells k and k+1
+// (one block holds 4A >= 16 fields); cell_half_apply runs the attempts on
+// those blocks, cell_half_fast draws them first.
+template <int A, int BB, bool Q0, bool DIS>
+__device__ __forceinline__ int32_t cell_half_apply(uint64_t& x, uint64_t m0, uint64_t m1,
+                                                    const CellCtx& c, const Blk& r0,
+                                                    const Blk& r1) {
+    constexpr int NA = 16;
+    static_assert(4 * A >= NA, "one block per cell and sub-sweep");
     static_assert(BB >= 0 && BB <= 2 && A * (5 + BB) <= 32, "field layout");
+    static_assert(!DIS || 3 + BB + (Q0 ? 0 : 1) <= 5, "marks in the offset");
     uint32_t h0 = (uint32_t)x, h1 = (uint32_t)(x >> 32);
+    const uint32_t f0 = (uint32_t)m0, f1 = (uint32_t)(m0 >> 32);
+    const uint32_t g0 = (uint32_t)m1, g1 = (uint32_t)(m1 >> 32);
     int32_t d0 = 0, d1 = 0;
-#pragma unroll
-    for (int blk = 0; blk < NB; ++blk) {
-        const uint32_t c2 = c.c2b | ((uint32_t)blk << 16);
-        const Blk r0 = philox(c.k, c.glo, c2, c.sample, c.k0, c.k1);
-        const Blk r1 = philox(c.k + 1u, c.glo, c2, c.sample, c.k0, c.k1);
+    {
 #pragma unroll
         for (int wd = 0; wd < 4; ++wd) {
 #pragma unroll
             for (int sl = 0; sl < A; ++sl) {
-                if (blk * PER + wd * A + sl >= NA) continue;
+                if (wd * A + sl >= NA) continue;
                 constexpr uint32_t W = 5u + (uint32_t)BB;
                 const uint32_t sh = (uint32_t)sl * W;
 #pragma unroll
@@ -347,7 +355,16 @@ __device__ __forceinline__ int32_t cell_half_fast(uint64_t& x, const CellCtx& c)
                         const uint32_t rs = sh >= 2 ? u >> (sh - 2) : u << (2 - sh);
                         off = insert_low2(sx, rs);
                     }
-                    const uint32_t F = (uint32_t)__builtin_amdgcn_sbfe((int32_t)c.lutP, off, 1);
+                    if (DIS) {
+                        // bit 0: forward mark at j; bit 1: backward mark at j+1
+                        uint32_t mk = (q ? f1 : f0) >> j;
+                        if (!Q0)
+                            mk = __builtin_amdgcn_bitop3_b32(mk, (q ? g1 : g0) >> j, 1u, 0xE4);
+                        off = __builtin_amdgcn_bitop3_b32(off, mk << (2 + BB),
+                                                          (1u << (2 + BB)) - 1u, 0xE4);
+                    }
+                    const uint32_t F = (uint32_t)__builtin_amdgcn_sbfe(
+                        (int32_t)(DIS ? c.lutD : c.lutP), off, 1);
                     h = xor_masked(h, 3u << j, F);
                     d += (int32_t)F;
                     if (!Q0) d += (int32_t)(F & ~sx & 2u);
@@ -357,6 +374,15 @@ __device__ __forceinline__ int32_t cell_half_fast(uint64_t& x, const CellCtx& c)
     }
     x = (uint64_t)h0 | ((uint64_t)h1 << 32);
     return Q0 ? -(d0 + d1) : d0 + d1;
+}
+
+// Draws of cells k and k+1 in the sub-sweep of c, then their attempts.
+template <int A, int BB, bool Q0, bool DIS>
+__device__ __forceinline__ int32_t cell_half_fast(uint64_t& x, uint64_t m0, uint64_t m1,
+                                                   const CellCtx& c) {
+    const Blk r0 = philox(c.k, c.glo, c.c2b, c.sample, c.k0, c.k1);
+    const Blk r1 = philox(c.k + 1u, c.glo, c.c2b, c.sample, c.k0, c.k1);
+    return cell_half_apply<A, BB, Q0, DIS>(x, m0, m1, c, r0, r1);
 }
 
 // Two lanes (Sec. 3): events 0 = A hops right on (x, x+1), 1 = B hops left
@@ -1253,7 +1279,7 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
                     }
                 } else if constexpr (HALF) {
                     cc.k = 2u * w;
-                    d = cell_half_fast<AV, BV, Q0, 16>(xa, cc);
+                    d = cell_half_fast<AV, BV, Q0, MODEL == kDisorder>(xa, m0, m1, cc);
                 } else if constexpr (FAST) {
                     cc.k = w;
                     if (MODEL == kTwoLane)
@@ -1426,7 +1452,7 @@ inline hipError_t launch_c(const SweepKernel& k, const SimDesc& one, const SimDe
                 case kF4B2: launch_q<MODEL, C, kF4B2>(k, one, descs, n_desc, grid, block, lds, st, ev0, ev1); return hipSuccess;
                 case kH6B0:
                 case kH5B1:
-                    if constexpr (MODEL == kPlain && C <= 8) {
+                    if constexpr ((MODEL == kPlain || MODEL == kDisorder) && C <= 8) {
                         if (k.variant == kH6B0)
                             launch_q<MODEL, C, kH6B0>(k, one, descs, n_desc, grid, block, lds, st, ev0, ev1);
                         else
@@ -1472,7 +1498,7 @@ inline bool variant_compiled(uint32_t C, uint32_t model, uint32_t variant) {
     if (variant == kSca) return model != kTwoLane || C <= 8;
     if (model == kTwoLane) return C <= 8 && (variant == kF4B0 || variant == kF1);
     if (variant == kF1) return C <= 8;  // one field per draw: 16 slots would spill
-    if (variant == kH6B0 || variant == kH5B1) return model == kPlain && C <= 8;
+    if (variant == kH6B0 || variant == kH5B1) return (model == kPlain || model == kDisorder) && C <= 8;
     return variant == kF5B0 || variant == kF4B1 || variant == kF4B2;
 }
 

@@ -384,7 +384,7 @@ static SweepKernel pick_kernel(const Resolved& r, uint32_t C) {
             if (sc.A == 1) v = 4;
         }
         if (v && sweep_variant_compiled(C, r.model, v)) k.variant = v;
-    } else if (sc.lam == 5 && sc.a == 16 && r.model == kPlain) {
+    } else if (sc.lam == 5 && sc.a == 16 && r.model != kTwoLane) {
         // cells of 32 sites, two sub-sweeps: the slot's halves are two cells
         uint32_t v = 0;
         if (sc.A == 6 && sc.b == 0) v = 7;

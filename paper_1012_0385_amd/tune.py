@@ -84,7 +84,9 @@ def lookup(kw: dict, samples: int, path: str = DEFAULT_TABLE) -> dict:
 
 
 def store(kw: dict, samples: int, best: dict, device: str, path: str = DEFAULT_TABLE) -> None:
-    """Write the entry of (kw, samples)'s class, replacing an entry of the same class."""
+    """Write the entry of (kw, samples)'s class, replacing an entry of the same
+    class, ahead of the first broader entry that also matches the run (the
+    first match wins)."""
     c = class_of(kw, samples)
     entries = [e for e in load_entries(path)
                if any(e[k] != c[k] for k in c)]
@@ -92,7 +94,8 @@ def store(kw: dict, samples: int, best: dict, device: str, path: str = DEFAULT_T
     for k in ("cell_log2", "subsweeps", "windows", "window_sweeps", "rings_per_wg"):
         e[k] = int(best.get(k, 0))
     e["note"] = "%.3e site-updates/s on %s" % (best.get("rate", 0.0), device)
-    entries.append(e)
+    at = next((i for i, x in enumerate(entries) if _matches(x, kw, samples)), len(entries))
+    entries.insert(at, e)
     with open(path, "w") as f:
         f.write("# Autotuned launch shapes and cell schedules (python -m paper_1012_0385_amd.tune)\n")
         f.write(HEADER)
@@ -119,10 +122,10 @@ def candidates(L: int, samples: int, cell_log2: int = 6):
 
 def schedules_for(kw: dict):
     """Cell schedules to try: both candidates where the caller left the cell
-    size and sub-sweeps open on a single-lane ring under the shifted
-    schedule, otherwise the caller's."""
+    size and sub-sweeps open on a single-lane ring (with or without columnar
+    disorder) under the shifted schedule, otherwise the caller's."""
     if (kw.get("model", 0) == 0 and kw.get("schedule", 0) == 0 and not kw.get("cell_log2")
-            and not kw.get("subsweeps") and not kw.get("slow_frac")):
+            and not kw.get("subsweeps")):
         return [dict(cell_log2=c, subsweeps=s) for c, s in SCHEDULES]
     return [dict()]
 

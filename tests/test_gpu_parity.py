@@ -150,8 +150,11 @@ def test_two_lane(orc, L, S, lane_rate, turn):
     compare(orc, kw, [0, 2, 15], 5)
 
 
-@pytest.mark.parametrize("rates", [dict(p=1.0, q=0.0), dict(p=0.5, q=0.5, init=1, density=0.4)],
-                         ids=["kpz", "ew"])
+@pytest.mark.parametrize("rates", [
+    dict(p=1.0, q=0.0), dict(p=0.5, q=0.5, init=1, density=0.4),
+    dict(p=1.0, q=0.0, slow_frac=0.1, slow_factor=0.5, samples_per_disorder=2),
+    dict(p=0.5, q=0.5, slow_frac=0.3, slow_factor=0.0, init=1, density=0.4),
+], ids=["kpz", "ew", "kpz-disorder", "ew-disorder-closed"])
 @pytest.mark.parametrize("shape", [dict(L=4096), dict(L=4160, windows=1),
                                    dict(L=1 << 17, windows=4, window_sweeps=255),
                                    dict(L=1 << 15, windows=3, window_sweeps=31)],
@@ -164,7 +167,8 @@ def test_half_word_cells(orc, rates, shape):
     sim = A.Simulation(A.make_params(samples=1, **kw))
     loop = sim.plan()["attempt_loop"]
     sim.close()
-    assert loop == (B.ASEP_LOOP_H6B0 if rates["q"] == 0 else B.ASEP_LOOP_H5B1)
+    nbits = 1 if rates["p"] < 1 or rates.get("slow_factor", 0) > 0 else 0
+    assert loop == (B.ASEP_LOOP_H6B0 if nbits == 0 else B.ASEP_LOOP_H5B1)
     compare(orc, kw, [0, 1, 7, 130, 300], 3)
 
 

@@ -57,6 +57,13 @@ RING_CASES = [
     # cells of 32 sites, two sub-sweeps: a slot's halves are two cells
     (dict(p=1.0, q=0.0, cell_log2=5, subsweeps=2), B.ASEP_LOOP_H6B0, 0),
     (dict(p=0.5, q=0.5, cell_log2=5, subsweeps=2, init=1, density=0.45), B.ASEP_LOOP_H5B1, 1),
+    # ... with columnar disorder: the marks of a half join the outcome's index
+    (dict(p=1.0, q=0.0, slow_frac=0.1, slow_factor=0.5, samples_per_disorder=2, cell_log2=5,
+          subsweeps=2), B.ASEP_LOOP_H5B1, 0),
+    (dict(p=1.0, q=1.0, slow_frac=0.2, slow_factor=0.5, init=1, density=0.5, cell_log2=5,
+          subsweeps=2), B.ASEP_LOOP_H5B1, 1),
+    (dict(p=1.0, q=0.0, slow_frac=0.3, slow_factor=0.0, cell_log2=5, subsweeps=2),
+     B.ASEP_LOOP_H6B0, 0),                                                      # slow bonds closed
 ]
 
 # ring size -> slots per lane of a whole single-lane ring

@@ -20,7 +20,8 @@ def test_schedules_tried_only_where_left_open():
         dict(cell_log2=6, subsweeps=4), dict(cell_log2=5, subsweeps=2)]
     assert tune.schedules_for(dict(L=1 << 17, p=1.0, subsweeps=4)) == [{}]
     assert tune.schedules_for(dict(L=1 << 16, model=1)) == [{}]
-    assert tune.schedules_for(dict(L=1 << 16, slow_frac=0.1)) == [{}]
+    assert len(tune.schedules_for(dict(L=1 << 16, slow_frac=0.1))) == 2
+    assert tune.schedules_for(dict(L=1 << 16, schedule=1)) == [{}]
 
 
 def test_table_roundtrip_and_library_agrees(tmp_path):
@@ -46,6 +47,21 @@ def test_table_roundtrip_and_library_agrees(tmp_path):
         assert plan["windows"] == 2
     finally:
         A.load_tuning(None)
+
+
+def test_stored_entry_goes_ahead_of_a_broader_one(tmp_path):
+    # the first matching entry wins, so a class tuned later must not end up
+    # behind a broad entry that also covers it
+    path = str(tmp_path / "t.txt")
+    with open(path, "w") as f:
+        f.write("0 0 0 10 26 1 65536 5 2 0 0 0   # broad\n")
+    kw = dict(L=4096, p=1.0, q=0.0)
+    assert tune.lookup(kw, 8, path)["windows"] == 0
+    tune.store(kw, 8, dict(windows=2, window_sweeps=7, rate=1.0), "gfx950", path)
+    entries = tune.load_entries(path)
+    assert [e["log2L_hi"] for e in entries] == [12, 26]
+    assert tune.lookup(kw, 8, path)["windows"] == 2
+    assert tune.lookup(dict(kw, L=1 << 20), 8, path)["cell_log2"] == 5
 
 
 def test_shipped_table_loads_and_covers_the_benchmark_workload():
