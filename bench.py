@@ -41,9 +41,10 @@ PEAK_SLOTS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock: 32-bit VALU sl
 # the low side), shared by the attempts whose fields its four words hold; an
 # attempt's update is the field's offset, the pair read, the outcome, the
 # flip of the two 32-bit halves of the word and the hop count (6 slots; a
-# cell of at most 32 sites flips within one 32-bit word: 5), plus
-# one slot for extracting compared bits (b > 0), one for a quenched mark and
-# two for a second lane (its pair and the event decode).
+# cell of at most 32 sites flips within one 32-bit word: 5; byte fields, which
+# cells of 32 sites take, hold the offset where the shifts read it: one
+# fewer), plus one slot for extracting compared bits (b > 0), one for a
+# quenched mark and two for a second lane (its pair and the event decode).
 PHILOX_SLOTS = 40
 UPDATE_SLOTS = 6
 
@@ -97,11 +98,14 @@ def alu_slots_per_attempt(sim):
     ell = 1 << p.cell_log2
     a = (4 * ell if two else ell) // p.subsweeps
     w = p.cell_log2 + (2 if two else 0) + p.rbits
-    per_word = 32 // w
+    byte_fields = p.cell_log2 == 5 and w <= 8
+    per_word = 4 if byte_fields else 32 // w
     nblk = -(-a // (4 * per_word))
     upd = UPDATE_SLOTS + (1 if p.rbits > 0 else 0) + (1 if p.slow_frac > 0 else 0) + (2 if two else 0)
     if p.cell_log2 <= 5 and not two:
         upd -= 1  # a cell of at most 32 sites flips within one 32-bit word
+    if byte_fields:
+        upd -= 1  # the offset is the low bits of its byte, read by the shifts
     return PHILOX_SLOTS * nblk / a + upd
 
 

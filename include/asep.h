@@ -186,9 +186,9 @@ enum {
     ASEP_LOOP_F1 = 4,        /* 1 per draw, compared bits at run time */
     ASEP_LOOP_F4B0_LANES = 5,/* two lanes, 64 attempts: 4 per draw, no compared bit */
     ASEP_LOOP_SUBLATTICE = 6,/* the paper's two-sub-lattice update */
-    ASEP_LOOP_H6B0 = 7,      /* ell = 32, 2 sub-sweeps: a slot's halves are two cells,
-                                6 fields per draw, no compared bit */
-    ASEP_LOOP_H5B1 = 8       /* ell = 32, 2 sub-sweeps: 5 fields per draw, 1 compared bit */
+    ASEP_LOOP_H4B0 = 7,      /* ell = 32, 2 sub-sweeps: a slot's halves are two cells,
+                                4 byte fields per draw, no compared bit */
+    ASEP_LOOP_H4B1 = 8       /* ell = 32, 2 sub-sweeps: 4 byte fields per draw, 1 compared bit */
 };
 typedef struct asep_plan {
     uint32_t windows;        /* 1: each ring whole in one workgroup; n >= 2: windows per ring */

@@ -73,6 +73,7 @@ class _Sched(ctypes.Structure):
         ("T_slow", ctypes.c_uint64),
         ("T_turn", ctypes.c_uint64),
         ("bc", ctypes.c_uint32),
+        ("jlow", ctypes.c_uint32),
     ]
 
 

@@ -229,7 +229,12 @@ int orc_lower(const orc_params *P, orc_sched *S) {
     S->b = (uint32_t)b;
     for (int i = 0; i < 4; ++i) S->T[i] = S->TB[i] >> (S->B - b);
     if (two) S->T[2] = S->TB[2] >> (32 - S->bc);
-    S->w = S->lam + S->ebits + S->b;
+    /* Cells of 32 sites whose field (position, event, compared bits) fits
+     * in 8 bits take the four bytes of a word as fields, the position in
+     * the low bits of its byte; every other schedule packs fields of
+     * lam + ebits + b bits with the position on top. */
+    S->jlow = (S->lam == 5 && S->lam + S->ebits + S->b <= 8) ? 1u : 0u;
+    S->w = S->jlow ? 8u : S->lam + S->ebits + S->b;
     S->A = 32 / S->w;
     S->per_block = 4 * S->A;
     S->T_init = orc_threshold(P->density, 32);
@@ -239,7 +244,8 @@ int orc_lower(const orc_params *P, orc_sched *S) {
 }
 
 /* Attempt m of cell k in sub-sweep g: block floor(m / 4A), word, slot, then
- * the field of w bits is split into (j | e | r) from the top. */
+ * the field of w bits is split into (j | e | r) from the top, or, with byte
+ * fields (jlow), into (r | e | j) from the top with j in the low lam bits. */
 static void attempt_fields(const orc_params *P, const orc_sched *S, uint32_t sample, uint64_t k,
                            uint64_t g, uint32_t m, uint32_t blockbuf[4], uint32_t *cached_blk,
                            uint32_t *j, uint32_t *e, uint32_t *r) {
@@ -254,6 +260,12 @@ static void attempt_fields(const orc_params *P, const orc_sched *S, uint32_t sam
     }
     uint32_t u = blockbuf[wd];
     uint64_t field = ((uint64_t)u >> (sl * S->w)) & ((((uint64_t)1) << S->w) - 1);
+    if (S->jlow) {
+        *j = (uint32_t)(field & ((1u << S->lam) - 1));
+        *e = (uint32_t)((field >> S->lam) & ((1u << S->ebits) - 1));
+        *r = (uint32_t)((field >> (S->lam + S->ebits)) & ((1u << S->b) - 1));
+        return;
+    }
     *r = (uint32_t)(field & ((((uint64_t)1) << S->b) - 1));
     *e = (uint32_t)((field >> S->b) & ((1u << S->ebits) - 1));
     *j = (uint32_t)(field >> (S->b + S->ebits));

@@ -42,6 +42,8 @@ typedef struct {
     uint64_t T_init, T_slow, T_turn; /* 32-bit thresholds */
     uint32_t bc;    /* two lanes, shifted schedule: bits compared for a lane change
                        (T[2] is the lane-change threshold at bc bits) */
+    uint32_t jlow;  /* cells of 32 sites whose field fits a byte: fields are the
+                       four bytes of a word, position in the low bits */
 } orc_sched;
 
 typedef struct {

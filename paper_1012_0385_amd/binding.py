@@ -39,8 +39,8 @@ ASEP_LOOP_F4B2 = 3
 ASEP_LOOP_F1 = 4
 ASEP_LOOP_F4B0_LANES = 5
 ASEP_LOOP_SUBLATTICE = 6
-ASEP_LOOP_H6B0 = 7
-ASEP_LOOP_H5B1 = 8
+ASEP_LOOP_H4B0 = 7
+ASEP_LOOP_H4B1 = 8
 
 
 class asep_params(ctypes.Structure):

@@ -141,7 +141,10 @@ __device__ inline void build_byte_tables(int32_t* tab1, int32_t* tab2) {
 // Attempt loops.  One call runs the `na` attempts of one cell in one
 // sub-sweep (Sec. 2.1's exchange rules under the shifted decomposition):
 // attempt m takes field (m mod A) of word ((m / A) mod 4) of Philox block
-// m / 4A; a field is [j | e | r] from the top (e only for two lanes).
+// m / 4A; a field is [j | e | r] from the top (e only for two lanes), or,
+// for cells of 32 sites whose field fits a byte, the fields are the bytes of
+// the word and each is [r | e | j] from the top (j in the low five bits, where
+// a shift by j reads it straight from the byte).
 // ---------------------------------------------------------------------------
 struct CellCtx {
     uint32_t k;       // cell index
@@ -150,6 +153,7 @@ struct CellCtx {
     uint32_t sample;
     uint32_t k0, k1;  // key
     uint32_t na, nblk, b, w, A;
+    uint32_t oj, oe, orr;  // bit offsets of j, e and r in a field
     uint32_t T0, T1, T2, T3;
     // With at most 2 compared bits: bit o says whether pair o mod 4 with
     // compared bits (o >> 2) mod 2^b hops (the pattern repeats every 2^(2+b)
@@ -188,8 +192,8 @@ __device__ __forceinline__ int32_t cell_ring_generic(uint64_t& x, uint64_t m0, u
             const uint32_t u = r.v[wd];
             for (uint32_t sl = 0; sl < c.A && m < c.na; ++sl, ++m) {
                 const uint32_t sh = sl * c.w;
-                const uint32_t rv = (u >> sh) & rmask;
-                const uint32_t j = (u >> (sh + c.b)) & cmask;
+                const uint32_t rv = (u >> (sh + c.orr)) & rmask;
+                const uint32_t j = (u >> (sh + c.oj)) & cmask;
                 const uint32_t pos = bb + j;
                 const uint32_t pr = (uint32_t)(x >> pos) & 3u;
                 uint32_t tp = c.T0, tq = c.T1;
@@ -312,63 +316,56 @@ __device__ __forceinline__ int32_t cell_ring_fast(uint64_t& x, uint64_t m0, uint
 // Single lane, ell = 32, two sub-sweeps per MCS (16 attempts per cell per
 // sub-sweep): the slot's two cells are its 32-bit halves (cells 2w and
 // 2w + 1), each updated with 32-bit operations, and their attempt chains
-// are independent, so one lane runs two of them side by side.  A fields per
-// 32-bit word, BB (<= 2) compared bits; the outcome is one bit of lutP
-// indexed by the pair and the compared bits, and the arithmetic shift makes
-// j = 31 (the bond leaving the cell) a no-op, as in cell_ring_fast.
-// With columnar disorder (DIS) the forward mark at j, and with backward hops
-// the backward mark at j + 1, join the pair and the compared bits in the
-// offset of lutD, as in cell_ring_fast; the marks come from the same half of
-// the slot's mark words.
-// The draws of the two cells are the first Philox block of cells k and k+1
-// (one block holds 4A >= 16 fields); cell_half_apply runs the attempts on
-// those blocks, cell_half_fast draws them first.
-template <int A, int BB, bool Q0, bool DIS>
+// are independent, so one lane runs two of them side by side.  The 16 fields
+// of a cell are the bytes of its Philox block, j in the low five bits of the
+// byte and BB (<= 2) compared bits above it: the shifts by j read it straight
+// from the byte (a byte operand select), so no instruction extracts it.  The
+// outcome is one bit of lutP indexed by the pair and the compared bits, and
+// the arithmetic shift makes j = 31 (the bond leaving the cell) a no-op, as
+// in cell_ring_fast.  With columnar disorder (DIS) the forward mark at j,
+// and with backward hops the backward mark at j + 1, join the pair and the
+// compared bits in the offset of lutD, as in cell_ring_fast; the marks come
+// from the same half of the slot's mark words.
+template <int BB, bool Q0, bool DIS>
 __device__ __forceinline__ int32_t cell_half_apply(uint64_t& x, uint64_t m0, uint64_t m1,
                                                     const CellCtx& c, const Blk& r0,
                                                     const Blk& r1) {
-    constexpr int NA = 16;
-    static_assert(4 * A >= NA, "one block per cell and sub-sweep");
-    static_assert(BB >= 0 && BB <= 2 && A * (5 + BB) <= 32, "field layout");
+    static_assert(BB >= 0 && BB <= 2, "field layout");
     static_assert(!DIS || 3 + BB + (Q0 ? 0 : 1) <= 5, "marks in the offset");
     uint32_t h0 = (uint32_t)x, h1 = (uint32_t)(x >> 32);
     const uint32_t f0 = (uint32_t)m0, f1 = (uint32_t)(m0 >> 32);
     const uint32_t g0 = (uint32_t)m1, g1 = (uint32_t)(m1 >> 32);
     int32_t d0 = 0, d1 = 0;
-    {
 #pragma unroll
-        for (int wd = 0; wd < 4; ++wd) {
+    for (int wd = 0; wd < 4; ++wd) {
 #pragma unroll
-            for (int sl = 0; sl < A; ++sl) {
-                if (wd * A + sl >= NA) continue;
-                constexpr uint32_t W = 5u + (uint32_t)BB;
-                const uint32_t sh = (uint32_t)sl * W;
+        for (int sl = 0; sl < 4; ++sl) {
+            const uint32_t sh = (uint32_t)sl * 8u;
 #pragma unroll
-                for (int q = 0; q < 2; ++q) {
-                    const uint32_t u = q ? r1.v[wd] : r0.v[wd];
-                    uint32_t& h = q ? h1 : h0;
-                    int32_t& d = q ? d1 : d0;
-                    const uint32_t j = bfe(u, sh + (uint32_t)BB, 5);
-                    const uint32_t sx = (uint32_t)((int32_t)h >> j);
-                    uint32_t off = sx;
-                    if (BB > 0) {
-                        const uint32_t rs = sh >= 2 ? u >> (sh - 2) : u << (2 - sh);
-                        off = insert_low2(sx, rs);
-                    }
-                    if (DIS) {
-                        // bit 0: forward mark at j; bit 1: backward mark at j+1
-                        uint32_t mk = (q ? f1 : f0) >> j;
-                        if (!Q0)
-                            mk = __builtin_amdgcn_bitop3_b32(mk, (q ? g1 : g0) >> j, 1u, 0xE4);
-                        off = __builtin_amdgcn_bitop3_b32(off, mk << (2 + BB),
-                                                          (1u << (2 + BB)) - 1u, 0xE4);
-                    }
-                    const uint32_t F = (uint32_t)__builtin_amdgcn_sbfe(
-                        (int32_t)(DIS ? c.lutD : c.lutP), off, 1);
-                    h = xor_masked(h, 3u << j, F);
-                    d += (int32_t)F;
-                    if (!Q0) d += (int32_t)(F & ~sx & 2u);
+            for (int q = 0; q < 2; ++q) {
+                const uint32_t u = q ? r1.v[wd] : r0.v[wd];
+                uint32_t& h = q ? h1 : h0;
+                int32_t& d = q ? d1 : d0;
+                // the byte holding j (its low five bits are what a shift
+                // uses; written as a byte extract so that the compiler folds
+                // it into the shifts' operand select)
+                const uint32_t jb = sl == 0 ? u : __builtin_amdgcn_ubfe(u, sh, 8);
+                const uint32_t j = jb & 31u;
+                const uint32_t sx = (uint32_t)((int32_t)h >> j);
+                uint32_t off = sx;
+                if (BB > 0) off = insert_low2(sx, u >> (sh + 3u));  // compared bits at 2
+                if (DIS) {
+                    // bit 0: forward mark at j; bit 1: backward mark at j+1
+                    uint32_t mk = (q ? f1 : f0) >> j;
+                    if (!Q0) mk = __builtin_amdgcn_bitop3_b32(mk, (q ? g1 : g0) >> j, 1u, 0xE4);
+                    off = __builtin_amdgcn_bitop3_b32(off, mk << (2 + BB), (1u << (2 + BB)) - 1u,
+                                                      0xE4);
                 }
+                const uint32_t F =
+                    (uint32_t)__builtin_amdgcn_sbfe((int32_t)(DIS ? c.lutD : c.lutP), off, 1);
+                h = xor_masked(h, 3u << j, F);
+                d += (int32_t)F;
+                if (!Q0) d += (int32_t)(F & ~sx & 2u);
             }
         }
     }
@@ -377,12 +374,12 @@ __device__ __forceinline__ int32_t cell_half_apply(uint64_t& x, uint64_t m0, uin
 }
 
 // Draws of cells k and k+1 in the sub-sweep of c, then their attempts.
-template <int A, int BB, bool Q0, bool DIS>
+template <int BB, bool Q0, bool DIS>
 __device__ __forceinline__ int32_t cell_half_fast(uint64_t& x, uint64_t m0, uint64_t m1,
                                                    const CellCtx& c) {
     const Blk r0 = philox(c.k, c.glo, c.c2b, c.sample, c.k0, c.k1);
     const Blk r1 = philox(c.k + 1u, c.glo, c.c2b, c.sample, c.k0, c.k1);
-    return cell_half_apply<A, BB, Q0, DIS>(x, m0, m1, c, r0, r1);
+    return cell_half_apply<BB, Q0, DIS>(x, m0, m1, c, r0, r1);
 }
 
 // Two lanes (Sec. 3): events 0 = A hops right on (x, x+1), 1 = B hops left
@@ -470,9 +467,9 @@ __device__ __forceinline__ int32_t cell_two_lane_generic(uint64_t& xa, uint64_t&
             const uint32_t u = r.v[wd];
             for (uint32_t sl = 0; sl < c.A && m < c.na; ++sl, ++m) {
                 const uint32_t sh = sl * c.w;
-                const uint32_t rv = (u >> sh) & rmask;
-                const uint32_t e = (u >> (sh + c.b)) & 3u;
-                const uint32_t j = (u >> (sh + c.b + 2)) & cmask;
+                const uint32_t rv = (u >> (sh + c.orr)) & rmask;
+                const uint32_t e = (u >> (sh + c.oe)) & 3u;
+                const uint32_t j = (u >> (sh + c.oj)) & cmask;
                 const uint32_t pos = bb + j;
                 const uint32_t pa = (uint32_t)(xa >> pos) & 3u;
                 const uint32_t pb = (uint32_t)(xb >> pos) & 3u;
@@ -759,8 +756,8 @@ enum Variant : int {
     kF1 = 4,    // 1 field per word, threshold bits at run time
     kF4B0 = 5,  // two lanes: 4 fields per word, no threshold bits
     kSca = 6,   // the paper's sub-lattice updates (both models, every slot shape)
-    kH6B0 = 7,  // ell = 32, two sub-sweeps: 6 fields per word, no threshold bits
-    kH5B1 = 8,  // ell = 32, two sub-sweeps: 5 fields per word, 1 threshold bit
+    kH4B0 = 7,  // ell = 32, two sub-sweeps: 4 byte fields per word, no threshold bits
+    kH4B1 = 8,  // ell = 32, two sub-sweeps: 4 byte fields per word, 1 threshold bit
 };
 
 template <int V>
@@ -788,12 +785,12 @@ struct VarInfo<kF4B0> {
     static constexpr int A = 4, BB = 0;
 };
 template <>
-struct VarInfo<kH6B0> {
-    static constexpr int A = 6, BB = 0;
+struct VarInfo<kH4B0> {
+    static constexpr int A = 4, BB = 0;
 };
 template <>
-struct VarInfo<kH5B1> {
-    static constexpr int A = 5, BB = 1;
+struct VarInfo<kH4B1> {
+    static constexpr int A = 4, BB = 1;
 };
 
 // Dynamic LDS of the sweep kernel, in this order:
@@ -897,7 +894,7 @@ template <int C, int MODEL, int V, bool Q0, bool MEAS, bool WU>
 __device__ __forceinline__ void sweep_body(const SimDesc& P) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int NPL = (MODEL == kTwoLane) ? 2 : 1;
-    constexpr bool HALF = V == kH6B0 || V == kH5B1;
+    constexpr bool HALF = V == kH4B0 || V == kH4B1;
     constexpr bool FAST = V != kGeneric && V != kSca && !HALF;
     constexpr int AV = VarInfo<V>::A;
     constexpr int BV = VarInfo<V>::BB;
@@ -961,6 +958,12 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
     cc.b = P.sc.b;
     cc.w = P.sc.w;
     cc.A = P.sc.A;
+    {
+        const uint32_t eb = MODEL == kTwoLane ? 2u : 0u;
+        cc.oj = P.sc.jlow ? 0u : P.sc.b + eb;
+        cc.oe = P.sc.jlow ? P.sc.lam : P.sc.b;
+        cc.orr = P.sc.jlow ? P.sc.lam + eb : 0u;
+    }
     cc.T0 = P.sc.T[0];
     cc.T1 = P.sc.T[1];
     cc.T2 = P.sc.T[2];
@@ -1279,7 +1282,7 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
                     }
                 } else if constexpr (HALF) {
                     cc.k = 2u * w;
-                    d = cell_half_fast<AV, BV, Q0, MODEL == kDisorder>(xa, m0, m1, cc);
+                    d = cell_half_fast<BV, Q0, MODEL == kDisorder>(xa, m0, m1, cc);
                 } else if constexpr (FAST) {
                     cc.k = w;
                     if (MODEL == kTwoLane)
@@ -1450,13 +1453,13 @@ inline hipError_t launch_c(const SweepKernel& k, const SimDesc& one, const SimDe
                 case kF5B0: launch_q<MODEL, C, kF5B0>(k, one, descs, n_desc, grid, block, lds, st, ev0, ev1); return hipSuccess;
                 case kF4B1: launch_q<MODEL, C, kF4B1>(k, one, descs, n_desc, grid, block, lds, st, ev0, ev1); return hipSuccess;
                 case kF4B2: launch_q<MODEL, C, kF4B2>(k, one, descs, n_desc, grid, block, lds, st, ev0, ev1); return hipSuccess;
-                case kH6B0:
-                case kH5B1:
+                case kH4B0:
+                case kH4B1:
                     if constexpr ((MODEL == kPlain || MODEL == kDisorder) && C <= 8) {
-                        if (k.variant == kH6B0)
-                            launch_q<MODEL, C, kH6B0>(k, one, descs, n_desc, grid, block, lds, st, ev0, ev1);
+                        if (k.variant == kH4B0)
+                            launch_q<MODEL, C, kH4B0>(k, one, descs, n_desc, grid, block, lds, st, ev0, ev1);
                         else
-                            launch_q<MODEL, C, kH5B1>(k, one, descs, n_desc, grid, block, lds, st, ev0, ev1);
+                            launch_q<MODEL, C, kH4B1>(k, one, descs, n_desc, grid, block, lds, st, ev0, ev1);
                         return hipSuccess;
                     }
                     return hipErrorInvalidValue;
@@ -1498,7 +1501,7 @@ inline bool variant_compiled(uint32_t C, uint32_t model, uint32_t variant) {
     if (variant == kSca) return model != kTwoLane || C <= 8;
     if (model == kTwoLane) return C <= 8 && (variant == kF4B0 || variant == kF1);
     if (variant == kF1) return C <= 8;  // one field per draw: 16 slots would spill
-    if (variant == kH6B0 || variant == kH5B1) return (model == kPlain || model == kDisorder) && C <= 8;
+    if (variant == kH4B0 || variant == kH4B1) return (model == kPlain || model == kDisorder) && C <= 8;
     return variant == kF5B0 || variant == kF4B1 || variant == kF4B2;
 }
 

@@ -266,7 +266,12 @@ static int resolve(const asep_params* in, int dev, Resolved* r) {
         // two lanes draw two words per plane (A and B pairs, or 64 sites)
         sc.nblk = two ? (sc.b + 1) / 2 : (sc.b + 3) / 4;
     } else {
-        sc.w = sc.lam + (uint32_t)ebits + sc.b;
+        // cells of 32 sites whose field fits a byte take the four bytes of a
+        // word as fields, the position in the low bits (read straight from
+        // the byte by the shifts that use it); other schedules pack fields of
+        // lam + ebits + b bits with the position on top
+        sc.jlow = (sc.lam == 5 && sc.lam + (uint32_t)ebits + sc.b <= 8) ? 1u : 0u;
+        sc.w = sc.jlow ? 8u : sc.lam + (uint32_t)ebits + sc.b;
         sc.A = 32 / sc.w;
         sc.nblk = (sc.a + 4 * sc.A - 1) / (4 * sc.A);
     }
@@ -387,8 +392,8 @@ static SweepKernel pick_kernel(const Resolved& r, uint32_t C) {
     } else if (sc.lam == 5 && sc.a == 16 && r.model != kTwoLane) {
         // cells of 32 sites, two sub-sweeps: the slot's halves are two cells
         uint32_t v = 0;
-        if (sc.A == 6 && sc.b == 0) v = 7;
-        if (sc.A == 5 && sc.b == 1) v = 8;
+        if (sc.jlow && sc.b == 0) v = 7;
+        if (sc.jlow && sc.b == 1) v = 8;
         if (v && sweep_variant_compiled(C, r.model, v)) k.variant = v;
     }
     k.q0 = !two && sc.T[1] == 0 && (r.model != kDisorder || sc.T[3] == 0);

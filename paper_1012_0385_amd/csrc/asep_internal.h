@@ -64,6 +64,8 @@ struct Sched {
     uint32_t T[4];  // ring {p, q, r p, r q}; two lanes {A hop, B hop, lane change}
     uint32_t bc;    // two lanes, shifted schedule: bits of a lane-change draw compared
                     // with T[2] (0: T[2] is 0 = never or 1 = always)
+    uint32_t jlow;  // fields are the bytes of a word, position in the low bits
+                    // (cells of 32 sites whose field fits in 8 bits)
     uint64_t T_init, T_slow, T_turn;  // 32-bit-draw thresholds (may equal 2^32)
 };
 

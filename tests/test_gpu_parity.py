@@ -168,8 +168,23 @@ def test_half_word_cells(orc, rates, shape):
     loop = sim.plan()["attempt_loop"]
     sim.close()
     nbits = 1 if rates["p"] < 1 or rates.get("slow_factor", 0) > 0 else 0
-    assert loop == (B.ASEP_LOOP_H6B0 if nbits == 0 else B.ASEP_LOOP_H5B1)
+    assert loop == (B.ASEP_LOOP_H4B0 if nbits == 0 else B.ASEP_LOOP_H4B1)
     compare(orc, kw, [0, 1, 7, 130, 300], 3)
+
+
+@pytest.mark.parametrize("kw", [
+    dict(L=4096 + 64, p=0.875, q=0.25, init=1),                 # 3 compared bits: generic loop
+    dict(L=4096, p=1.0, q=0.0, subsweeps=1),                     # 32 attempts: two blocks per cell
+    dict(L=4096, p=0.9375, q=0.0),                               # 9-bit fields: packed, not bytes
+    dict(L=2048, model=1, init=1, density=0.3, p=1.0, q=1.0, lane_rate=0.1,
+         turn_frac=0.05),                                        # two lanes, 7-bit fields: bytes
+], ids=["b3-ragged", "S1", "b4-packed", "two-lane"])
+def test_byte_fields_in_generic_loops(orc, kw):
+    # cells of 32 sites outside the fast loop: the generic loops read the
+    # fields' offsets from the schedule (bytes with the position low, or
+    # packed fields with the position on top)
+    kw = dict(dict(cell_log2=5, subsweeps=2, seed=13, stream=9), **kw)
+    compare(orc, kw, [0, 1, 6, 40], 3)
 
 
 @pytest.mark.parametrize("kw,samples", [

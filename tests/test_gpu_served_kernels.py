@@ -55,15 +55,15 @@ RING_CASES = [
      B.ASEP_LOOP_GENERIC, 1),                                                   # 3 bits: 3 per draw
     (dict(p=0.9, q=0.3, cell_log2=5, subsweeps=2, init=1), B.ASEP_LOOP_GENERIC, 1),
     # cells of 32 sites, two sub-sweeps: a slot's halves are two cells
-    (dict(p=1.0, q=0.0, cell_log2=5, subsweeps=2), B.ASEP_LOOP_H6B0, 0),
-    (dict(p=0.5, q=0.5, cell_log2=5, subsweeps=2, init=1, density=0.45), B.ASEP_LOOP_H5B1, 1),
+    (dict(p=1.0, q=0.0, cell_log2=5, subsweeps=2), B.ASEP_LOOP_H4B0, 0),
+    (dict(p=0.5, q=0.5, cell_log2=5, subsweeps=2, init=1, density=0.45), B.ASEP_LOOP_H4B1, 1),
     # ... with columnar disorder: the marks of a half join the outcome's index
     (dict(p=1.0, q=0.0, slow_frac=0.1, slow_factor=0.5, samples_per_disorder=2, cell_log2=5,
-          subsweeps=2), B.ASEP_LOOP_H5B1, 0),
+          subsweeps=2), B.ASEP_LOOP_H4B1, 0),
     (dict(p=1.0, q=1.0, slow_frac=0.2, slow_factor=0.5, init=1, density=0.5, cell_log2=5,
-          subsweeps=2), B.ASEP_LOOP_H5B1, 1),
+          subsweeps=2), B.ASEP_LOOP_H4B1, 1),
     (dict(p=1.0, q=0.0, slow_frac=0.3, slow_factor=0.0, cell_log2=5, subsweeps=2),
-     B.ASEP_LOOP_H6B0, 0),                                                      # slow bonds closed
+     B.ASEP_LOOP_H4B0, 0),                                                      # slow bonds closed
 ]
 
 # ring size -> slots per lane of a whole single-lane ring

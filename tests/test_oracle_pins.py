@@ -83,6 +83,27 @@ def test_draw_packing(orc, p, q, b, A):
         assert t * 2 ** (s["B"] - b) == tb
 
 
+@pytest.mark.parametrize("kw,jlow,A", [
+    (dict(cell_log2=5, subsweeps=2, p=1.0, q=0.0), 1, 4),                 # b = 0
+    (dict(cell_log2=5, subsweeps=2, p=0.5, q=0.5), 1, 4),                 # b = 1
+    (dict(cell_log2=5, subsweeps=2, p=0.875, q=0.25), 1, 4),              # b = 3: 8 bits
+    (dict(cell_log2=5, subsweeps=2, p=0.9375, q=0.0), 0, 3),              # b = 4: 9 bits
+    (dict(cell_log2=4, subsweeps=1, p=1.0, q=0.0), 0, 8),                 # 16-site cells
+    (dict(cell_log2=6, subsweeps=4, p=1.0, q=0.0), 0, 5),                 # 64-site cells
+    (dict(cell_log2=5, subsweeps=2, model=1, p=1.0, q=1.0, lane_rate=0.5), 1, 4),  # 7 bits
+    (dict(cell_log2=5, subsweeps=2, model=1, p=0.75, q=1.0, lane_rate=0.5), 0, 3),  # 9 bits
+])
+def test_byte_fields_for_32_site_cells(orc, kw, jlow, A):
+    # cells of 32 sites whose field fits in 8 bits take the four bytes of a
+    # word as fields (the position in the low bits); every other schedule
+    # packs fields of lam + ebits + b bits
+    s = orc.lower(orc.Params(L=4096, **kw))
+    assert s["jlow"] == jlow and s["A"] == A
+    ebits = 2 if kw.get("model", 0) == 1 else 0
+    assert s["w"] == (8 if jlow else kw["cell_log2"] + ebits + s["b"])
+    assert s["per_block"] == 4 * A
+
+
 # --------------------------------------------------------------------------- init, heights
 @pytest.mark.parametrize("L", [128, 4096, 2**17])
 def test_flat_start_intrinsic_width(orc, L):
