@@ -261,6 +261,18 @@ def cpu_baseline(times_all, n_rings, t_cut, full_ring=False, sched=(6, 4)):
         oracle.run(P, sample, times)
         return time.perf_counter() - t0
 
+    def as_run(kw, samples):
+        # the cell schedule the GPU run takes from the tuning table, where the
+        # workload leaves it open
+        from paper_1012_0385_amd import tune
+
+        if kw.get("cell_log2") or kw.get("subsweeps") or kw.get("schedule", 0):
+            return kw
+        e = tune.lookup(kw, samples)
+        if e.get("cell_log2") and e.get("subsweeps"):
+            return dict(kw, cell_log2=e["cell_log2"], subsweeps=e["subsweeps"])
+        return kw
+
     times = prefix(times_all, t_cut)
     jobs = []
     for name, p, q, sid in MODELS:
@@ -286,7 +298,7 @@ def cpu_baseline(times_all, n_rings, t_cut, full_ring=False, sched=(6, 4)):
     others = {}
     for name, cut, cut1 in (("disorder_L2p16", 1000, 1000), ("two_lane_L2p16", 1000, 500)):
         kw, samples, t_max, _, desc = W.WORKLOADS[name]
-        P = oracle.Params(**kw)
+        P = oracle.Params(**as_run(kw, samples))
         per = kw["L"] * (4 if kw.get("model", 0) == 1 else 1)
         full = W.geometric_times(t_max)
         dt = pool_run([(P, i, prefix(full, cut)) for i in range(16)])
@@ -300,7 +312,7 @@ def cpu_baseline(times_all, n_rings, t_cut, full_ring=False, sched=(6, 4)):
     jobs, work = [], 0
     for r in reqs:
         cut = max(1, min(r.t_max, (1 << 28) // r.L))
-        jobs.append((oracle.Params(**r.kwargs()), 0, prefix(r.times, cut)))
+        jobs.append((oracle.Params(**as_run(r.kwargs(), r.samples)), 0, prefix(r.times, cut)))
         work += r.L * cut
     dt = pool_run(jobs)
     others["served_mix"] = {"value": work / dt, "cores": min(threads, len(jobs)),

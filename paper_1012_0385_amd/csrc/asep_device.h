@@ -1029,7 +1029,10 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
     // whole rings of at most one wave each (lanes_per_ring a power of two
     // up to 64, so no ring straddles two waves) exchange across lanes
     const bool wsync = !seg && Tr <= 64u && (64u % Tr) == 0u;
-    uint32_t sig = 0, off = 0, buf = 0;
+    // bo: word offset of this sub-sweep's half of the double-buffered
+    // exchange area (toggles between 0 and block * NPL)
+    uint32_t sig = 0, off = 0, bo = 0;
+    const uint32_t bstride = block * NPL;
     // word held by this lane's slot 0: (base + off + base_slot) mod nw
     uint32_t wb = (uint32_t)(((uint64_t)base + base_slot) % nw);
     int64_t J = 0;
@@ -1055,7 +1058,6 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
             na_ = shfl_u64(sa[0], src);
             if (MODEL == kTwoLane) nb_ = shfl_u64(sb[0], src);
         } else {
-            const uint32_t bo = buf * block * NPL;
             xw[bo] = sa[0];
             if (MODEL == kTwoLane) xw[bo + 1] = sb[0];
             __syncthreads();
@@ -1078,7 +1080,7 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
             if (!seg && off == nw) off = 0;
         }
         sig = sig_new;
-        buf ^= 1u;
+        bo ^= bstride;
     };
 
     // Heights and exact sums of a whole ring (slots at shift 0).
@@ -1169,29 +1171,25 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
     uint32_t shv = 0;
     uint32_t ri = 0;
     // sub-sweeps of this launch (at most 2^30: the host splits longer runs);
-    // the hops of the lane's own cells gather in J32 and fold into J every
-    // 4096 sub-sweeps and before a measurement (a slot takes at most 256
-    // attempts per sub-sweep and a lane at most 16 slots, so |J32| < 2^25)
+    // the hops of the lane's own cells add into the 64-bit J every
+    // sub-sweep (one sign extension and one 64-bit add)
     const uint32_t nsub = (uint32_t)(P.g1 - P.g0);
-    int32_t J32 = 0;
     // first slot of this lane's wave (windows: one ring per workgroup, lt = tid)
     const uint32_t wave_slot0 = __builtin_amdgcn_readfirstlane(lt & ~63u) * (uint32_t)C;
+    // sub-sweeps in which this wave's slots can still reach the output
+    // (windows; whole rings: all)
+    const uint32_t tlive =
+        !seg ? 0xFFFFFFFFu : (nout + nsub > wave_slot0 ? nout + nsub - wave_slot0 : 0u);
     for (uint32_t t = 0;; ++t) {
         const uint64_t g = P.g0 + t;
         if constexpr (MEAS) {
             while (ri < P.n_rec && P.rec_g[ri] == g) {
-                J += J32;
-                J32 = 0;
                 shift_to(0);  // uniform call: rings of one workgroup may differ in sig
                 measure(ri);
                 ++ri;
             }
         }
         if (t >= nsub) break;
-        if ((t & 4095u) == 4095u) {
-            J += J32;
-            J32 = 0;
-        }
         // SCA step: single lane even / odd pairs; two lanes even pairs,
         // A -> B, odd pairs, B -> A.  g is the same for the whole workgroup,
         // so skipping the exchange when the frame stays is a uniform branch.
@@ -1244,7 +1242,7 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
         // change, and nsub - t of them follow this sub-sweep, so slots at or
         // past nout + nsub - t can no longer reach the output (nor are they
         // owned).  A wave whose first slot is there skips its attempts.
-        const bool live = !seg || t + wave_slot0 < nout + nsub;
+        const bool live = t < tlive;
 #pragma unroll
         for (int i = 0; i < C; ++i) {
             if (live && i < cnt) {
@@ -1305,9 +1303,8 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
                 if (!seg || pos - lm < nout) dj += d;
             }
         }
-        J32 += dj;
+        J += dj;
     }
-    J += J32;
     shift_to(0);
 #pragma unroll
     for (int i = 0; i < C; ++i) {
