@@ -56,9 +56,9 @@ UPDATE_SLOTS = 6
 # only for the kernel sources they were taken on (SHA-256 prefix below) and
 # for that launch shape; otherwise the bench reports traffic as unknown.
 SWEEP_TRAFFIC = {
-    "src_sha256": "9cd9babb0961de85",
+    "src_sha256": "2b68c8e3e8f0ce3b",
     "launch_shape": {"windows": 3, "window_sweeps": 63, "rings_per_wg": 0},
-    "fetch_kib": 636.12,   # KPZ 633.12, EW 639.12
+    "fetch_kib": 634.37,   # KPZ 632.62, EW 636.12
     "write_kib": 1034.0,
     "fetch_scale": 2.0,    # 4 GiB copy: FETCH_SIZE 2097206 KiB
     "write_scale": 1.0,    # 4 GiB copy: WRITE_SIZE 4194304 KiB
