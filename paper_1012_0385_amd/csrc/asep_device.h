@@ -171,7 +171,6 @@ struct CellCtx {
     // whether the lane change (A -> B, B -> A) finds a particle on its side
     // and a hole on the other.
     uint32_t c2c, bc;
-    uint64_t Tw;  // lane change: a draw u moves iff u < Tw (T2 << (32 - bc))
     uint64_t lut2;
 };
 
@@ -399,7 +398,27 @@ __device__ __forceinline__ int32_t cell_half_fast(uint64_t& x, uint64_t m0, uint
 struct ChangeDraws {
     uint32_t u0, u1, u2, u3;
     uint32_t n;  // candidates so far
+    // fast loops: acceptance of the first four candidates (bit i for
+    // candidate i, taken from bit 0 and shifted out) above a sentinel at
+    // bit 4, which reaches bit 0 exactly when a fifth candidate comes.  With
+    // no compared bit (bc = 0) every decision is T2 != 0: all ones or zero,
+    // which the arithmetic shift keeps and which never equals the sentinel.
+    int32_t m;
 };
+
+// The fast loops' form of the cell's four up-front lane-change draws: their
+// decisions as bits (the same comparisons change_accept makes).
+__device__ __forceinline__ void change_begin_bits(ChangeDraws& d, const CellCtx& c) {
+    if (c.bc) {
+        const Blk r = philox(c.k, c.glo, c.c2c, c.sample, c.k0, c.k1);
+        const uint32_t sh = 32u - c.bc;
+        d.m = (int32_t)(0x10u | ((r.v[0] >> sh) < c.T2 ? 1u : 0u) |
+                        ((r.v[1] >> sh) < c.T2 ? 2u : 0u) | ((r.v[2] >> sh) < c.T2 ? 4u : 0u) |
+                        ((r.v[3] >> sh) < c.T2 ? 8u : 0u));
+    } else {
+        d.m = c.T2 != 0 ? -1 : 0;
+    }
+}
 
 __device__ __forceinline__ void change_begin(ChangeDraws& d, const CellCtx& c) {
     d.n = 0;
@@ -417,8 +436,16 @@ __device__ __forceinline__ void change_begin(ChangeDraws& d, const CellCtx& c) {
 // needed; otherwise a fifth candidate sets `over` (its outcome is not used).
 template <bool LATE>
 __device__ __forceinline__ bool change_accept(ChangeDraws& d, const CellCtx& c, bool& over) {
-    const uint32_t n = d.n++;
+    if constexpr (!LATE) {
+        // decisions of change_begin_bits; the sentinel at bit 0 marks a
+        // fifth candidate
+        over |= d.m == 1;
+        const bool a = (d.m & 1) != 0;
+        d.m >>= 1;
+        return a;
+    }
     if (c.bc == 0) return c.T2 != 0;
+    const uint32_t n = d.n++;
     uint32_t u;
     if (n < 4) {
         u = n == 0 ? d.u0 : n == 1 ? d.u1 : n == 2 ? d.u2 : d.u3;
@@ -495,7 +522,7 @@ __device__ __forceinline__ int32_t cell_two_lane_fast(uint64_t& xa, uint64_t& xb
     constexpr int NB = (NA + PER - 1) / PER;
     int32_t dj = 0;
     ChangeDraws cd;
-    change_begin(cd, c);
+    change_begin_bits(cd, c);
     bool over = false;
     const uint64_t xa0 = xa, xb0 = xb;
 #pragma unroll
@@ -539,17 +566,12 @@ __device__ __forceinline__ int32_t cell_two_lane_fast(uint64_t& xa, uint64_t& xb
                     // stay live across the lane-change branches below
                     asm volatile("" : "+v"(dj));
                     if (FC) {
-                        // the next of the four draws made up front (a
+                        // the next of the four decisions made up front (a
                         // fifth candidate sends the cell to the replay)
-                        const uint32_t n = cd.n;
-                        const uint32_t uc = n == 0u ? cd.u0 : n == 1u ? cd.u1 : n == 2u ? cd.u2 : cd.u3;
-                        over |= n >= 4u;
-                        cd.n = n + 1u;
-                        if ((uint64_t)uc < c.Tw) {
-                            const uint64_t m1 = 1ull << j;
-                            xa ^= m1;
-                            xb ^= m1;
-                        }
+                        const bool acc = change_accept<false>(cd, c, over);
+                        const uint64_t m1 = acc ? 1ull << j : 0ull;
+                        xa ^= m1;
+                        xb ^= m1;
                     }
                 } else {
                     const uint32_t b = BB >= 0 ? (uint32_t)BB : c.b;
@@ -972,7 +994,6 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
     cc.lutD = 0;
     cc.c2c = 0;
     cc.bc = P.sc.bc;
-    cc.Tw = (uint64_t)P.sc.T[2] << (32u - P.sc.bc);
     cc.lut2 = 0;
     if (MODEL == kTwoLane) {
         for (uint32_t o = 0; o < 32; ++o) {

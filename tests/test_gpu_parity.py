@@ -218,6 +218,8 @@ def test_two_lane_many_lane_changes(orc, lane_rate):
     kw = dict(L=4096, model=1, init=1, density=0.5, p=1.0, q=1.0, lane_rate=lane_rate,
               turn_frac=1.0, seed=5, stream=9)
     compare(orc, kw, [0, 1, 4, 9], 3)
+    # the same with cells of 32 sites (the generic loop, byte fields)
+    compare(orc, dict(kw, cell_log2=5, subsweeps=2), [0, 1, 4, 9], 3)
 
 
 def test_two_lane_general_rates(orc):

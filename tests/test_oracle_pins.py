@@ -229,9 +229,10 @@ def test_disorder_special_cases(orc):
     assert sq is None and abs(sp.mean() - 0.1) < 0.005
 
 
-def test_two_lane_conservation_and_decoupling(orc):
+@pytest.mark.parametrize("sched", [(6, 4), (5, 2)], ids=["64-site", "32-site"])
+def test_two_lane_conservation_and_decoupling(orc, sched):
     P = orc.Params(L=1024, model=orc.TWO_LANE, init=orc.INIT_BERNOULLI, density=0.3, p=1.0,
-                   q=1.0, lane_rate=0.1, turn_frac=0.05, subsweeps=4)
+                   q=1.0, lane_rate=0.1, turn_frac=0.05, cell_log2=sched[0], subsweeps=sched[1])
     r = orc.run(P, 2, [0, 10, 30])
     assert len(set(r.N.tolist())) == 1
     # no lane changes: each lane keeps its particle number
