@@ -57,7 +57,7 @@ UPDATE_SLOTS = 6
 # for that launch shape; otherwise the bench reports traffic as unknown.
 SWEEP_TRAFFIC = {
     "src_sha256": "2b68c8e3e8f0ce3b",
-    "launch_shape": {"windows": 3, "window_sweeps": 63, "rings_per_wg": 0},
+    "launch_shape": {"windows": 4, "window_sweeps": 255, "rings_per_wg": 0},
     "fetch_kib": 634.37,   # KPZ 632.62, EW 636.12
     "write_kib": 1034.0,
     "fetch_scale": 2.0,    # 4 GiB copy: FETCH_SIZE 2097206 KiB

@@ -221,7 +221,11 @@ if __name__ == "__main__":
     ap.add_argument("--only", type=int, default=-1, help="tune only job i")
     ap.add_argument("--out", default=DEFAULT_TABLE)
     ap.add_argument("--refine-t-max", type=int, default=0,
-                    help="re-time the best candidates over a run of this many MCS (0: no)")
+                    help="re-time the best candidates over a run of this many MCS (0: no); "
+                         "the job's own length decides best, since short probes with dense "
+                         "measurements favour short launches")
+    ap.add_argument("--refine-top", type=int, default=3,
+                    help="how many of the probes' best candidates the long run re-times")
     args = ap.parse_args()
     from .sim import load_tuning, sample_times
 
@@ -239,7 +243,7 @@ if __name__ == "__main__":
             rt = sample_times(30, 1.05, args.refine_t_max)
             if rt[-1] != args.refine_t_max:
                 rt.append(args.refine_t_max)
-        best = tune(kws, samples, jt, verbose=True, refine_times=rt)
+        best = tune(kws, samples, jt, verbose=True, refine_times=rt, top=args.refine_top)
         print("best", best, flush=True)
         if best:
             store(kws[0], samples, best, dev, args.out)
