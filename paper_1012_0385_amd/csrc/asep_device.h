@@ -15,6 +15,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "asep_internal.h"
 
 namespace asep {
@@ -1065,14 +1067,19 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
     // lane nxt's first slot), measured or stored.
     uint64_t* const xw = xch + (size_t)tid * NPL;
     uint64_t* const xr = xch + (size_t)nxt * NPL;
-    auto shift_to = [&](uint32_t sig_new) {
+    // LAY: 0 = windows or whole rings as `seg` says, 1 = windows, 2 = whole
+    // rings (the sub-sweep loop runs in the form of its launch, so that the
+    // bookkeeping of the other form drops out)
+    auto shift_to = [&](uint32_t sig_new, auto lay) {
+        constexpr int LAY = decltype(lay)::value;
+        const bool sg = LAY == 0 ? seg : LAY == 1;
         const uint32_t delta = (sig_new + 64u - sig) & 63u;
         // frames are below 64: the start moved back (wrapped) exactly when
         // sig + delta overshoots sig_new (written so that a wave-uniform frame
         // keeps both in scalar registers)
         const bool wrap = sig + delta != sig_new;
         uint64_t na_ = 0, nb_ = 0;
-        if (wsync) {
+        if (!sg && wsync) {
             // the ring lies inside one wave: read the neighbour lane's first
             // slot across lanes (every lane takes part), no barrier
             const int src = (int)(nxt & 63u);
@@ -1098,7 +1105,7 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
         if (wrap) {
             off += 1;
             wb = (wb + 1 == nw) ? 0u : wb + 1;
-            if (!seg && off == nw) off = 0;
+            if (!sg && off == nw) off = 0;
         }
         sig = sig_new;
         bo ^= bstride;
@@ -1201,11 +1208,14 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
     // (windows; whole rings: all)
     const uint32_t tlive =
         !seg ? 0xFFFFFFFFu : (nout + nsub > wave_slot0 ? nout + nsub - wave_slot0 : 0u);
+    auto sub_sweeps = [&](auto lay) {
+    constexpr int LAY = decltype(lay)::value;
+    const bool sg = LAY == 0 ? seg : LAY == 1;
     for (uint32_t t = 0;; ++t) {
         const uint64_t g = P.g0 + t;
         if constexpr (MEAS) {
             while (ri < P.n_rec && P.rec_g[ri] == g) {
-                shift_to(0);  // uniform call: rings of one workgroup may differ in sig
+                shift_to(0, lay);  // uniform call: rings of one workgroup may differ in sig
                 measure(ri);
                 ++ri;
             }
@@ -1219,7 +1229,7 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
             // the odd pairs are the only step in the frame starting at odd
             // sites; lane changes draw their bits in the even frame
             const uint32_t frame = (MODEL == kTwoLane) ? (step == 2u ? 1u : 0u) : step;
-            if (frame != sig) shift_to(frame);
+            if (frame != sig) shift_to(frame, lay);
             cc.c2b = (kTagSublattice << 28) | (uint32_t)((g >> 32) & 0xFFFFu);
         } else {
             uint32_t sw;
@@ -1253,7 +1263,7 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
                 const uint32_t gq = (uint32_t)(g & 3u);
                 sw = gq == 0 ? shblk[0] : gq == 1 ? shblk[1] : gq == 2 ? shblk[2] : shblk[3];
             }
-            shift_to(sw & cmask);
+            shift_to(sw & cmask, lay);
             cc.c2b = (kTagAttempt << 28) | (uint32_t)((g >> 32) & 0xFFFFu);
             cc.c2c = (kTagChange << 28) | (uint32_t)((g >> 32) & 0xFFFFu);
         }
@@ -1263,7 +1273,7 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
         // change, and nsub - t of them follow this sub-sweep, so slots at or
         // past nout + nsub - t can no longer reach the output (nor are they
         // owned).  A wave whose first slot is there skips its attempts.
-        const bool live = t < tlive;
+        const bool live = !sg || t < tlive;
 #pragma unroll
         for (int i = 0; i < C; ++i) {
             if (live && i < cnt) {
@@ -1275,7 +1285,7 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
                 uint64_t m0 = 0, m1 = 0;
                 if (MODEL != kPlain && P.mplanes > 0) {
                     uint32_t ia, ib;
-                    if (seg) {
+                    if (sg) {
                         ia = min(pos, mwords - 2);
                         ib = ia + 1;
                     } else {
@@ -1321,12 +1331,22 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
                 sa[i] = xa;
                 if (MODEL == kTwoLane) sb[i] = xb;
                 // a window counts the hops of the cells it owns
-                if (!seg || pos - lm < nout) dj += d;
+                if (!sg || pos - lm < nout) dj += d;
             }
         }
         J += dj;
     }
-    shift_to(0);
+    };
+    // measuring kernels run whole rings only; launches without measurements
+    // take the loop of their form
+    if constexpr (MEAS) {
+        sub_sweeps(std::integral_constant<int, 0>{});
+    } else if (seg) {
+        sub_sweeps(std::integral_constant<int, 1>{});
+    } else {
+        sub_sweeps(std::integral_constant<int, 2>{});
+    }
+    shift_to(0, std::integral_constant<int, 0>{});
 #pragma unroll
     for (int i = 0; i < C; ++i) {
         if (i < cnt) {
