@@ -407,6 +407,14 @@ def served_mix_leg(A, W, n_req, load, n_lat=200, seed=5):
     _, t_served = serve(probe, live_arrivals=False)
     cap_plain = total / t_plain
     cap_served = total / t_served
+    out = {
+        "workload": "served mix: Poisson requests, L=64*ceil(2^U[10,26]/64), KPZ/EW/disorder, "
+                    "t_max=10^U[3,5], samples=2^U[0,8], capped at 2^38 attempts",
+        "capacity": {"served": cap_served, "plain": cap_plain, "unit": "site-updates/s",
+                     "requests": n_req, "site_updates": total},
+    }
+    if n_lat <= 0:
+        return out
     # Poisson arrivals at `load` x the plain capacity
     rate = load * cap_plain / (total / n_req)
     reqs = W.served_mix(n_lat, rate, seed=seed)
@@ -414,19 +422,14 @@ def served_mix_leg(A, W, n_req, load, n_lat=200, seed=5):
     lat_s, span_s = serve(reqs, live_arrivals=True)
     lat_p = plain_live(reqs)
     pct = lambda v, q: float(np.percentile(np.array(v), q))
-    return {
-        "workload": "served mix: Poisson requests, L=64*ceil(2^U[10,26]/64), KPZ/EW/disorder, "
-                    "t_max=10^U[3,5], samples=2^U[0,8], capped at 2^38 attempts",
-        "capacity": {"served": cap_served, "plain": cap_plain, "unit": "site-updates/s",
-                     "requests": n_req, "site_updates": total},
-        "latency": {"requests": n_lat, "load": load, "arrival_rate_per_s": rate,
-                    "site_updates": work_lat, "measured": "live, both forms",
-                    "served_s": {"p50": pct(lat_s, 50), "p99": pct(lat_s, 99),
-                                 "max": max(lat_s)},
-                    "plain_s": {"p50": pct(lat_p, 50), "p99": pct(lat_p, 99),
-                                "max": max(lat_p)},
-                    "served_throughput_at_load": work_lat / span_s},
-    }
+    out["latency"] = {"requests": n_lat, "load": load, "arrival_rate_per_s": rate,
+                      "site_updates": work_lat, "measured": "live, both forms",
+                      "served_s": {"p50": pct(lat_s, 50), "p99": pct(lat_s, 99),
+                                   "max": max(lat_s)},
+                      "plain_s": {"p50": pct(lat_p, 50), "p99": pct(lat_p, 99),
+                                  "max": max(lat_p)},
+                      "served_throughput_at_load": work_lat / span_s}
+    return out
 
 
 HBM_PEAK = 8.0e12  # B/s
