@@ -1039,6 +1039,9 @@ void sim_describe(const asep_sim* s, asep_params* resolved, asep_plan* plan) {
     fill_plan(s->plan, plan);
 }
 hipStream_t sim_stream(const asep_sim* s) { return s->stream; }
+void sim_set_stream(asep_sim* s, hipStream_t st) {
+    if (!s->own_stream) s->stream = st;
+}
 uint32_t sim_samples(const asep_sim* s) { return s->r.P.samples; }
 uint64_t sim_attempts_per_mcs(const asep_sim* s) {
     return (uint64_t)s->r.P.samples * s->r.P.L * (s->r.planes == 2 ? 4 : 1);

@@ -149,6 +149,9 @@ int sim_create_borrowed(const asep_params* p, void* state, size_t state_bytes, v
 uint64_t sim_max_quantum_mcs(const asep_sim* s);
 void sim_describe(const asep_sim* s, asep_params* resolved, asep_plan* plan);
 hipStream_t sim_stream(const asep_sim* s);
+// A borrowed simulation's next work goes to `st` (its earlier work must be
+// complete: nothing orders the two streams).
+void sim_set_stream(asep_sim* s, hipStream_t st);
 uint32_t sim_samples(const asep_sim* s);
 uint64_t sim_attempts_per_mcs(const asep_sim* s);
 int sim_run_async(asep_sim* s, const uint64_t* times_pinned, uint32_t n, uint64_t t_end,

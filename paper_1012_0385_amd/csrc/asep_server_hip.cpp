@@ -1,9 +1,9 @@
 // asep_server_hip.cpp -- the request loop's device executor.
 //
 // Requests live in one device arena (the configured memory budget, first
-// fit), each on one stream of a fixed pool, with an event marking the end of
-// its queued work.  A quantum is one asynchronous run segment of the
-// request's simulation; several small whole-ring requests with the same
+// fit), with an event marking the end of their queued work.  A quantum is one
+// asynchronous run segment of the request's simulation, queued on the next
+// stream of a fixed pool; several small whole-ring requests with the same
 // kernel shape share one packed launch on a free pool stream (their
 // descriptors in device memory).
 //
@@ -136,7 +136,7 @@ class PinnedPool {
     std::vector<void*> all_;
 };
 
-constexpr uint32_t kStreams = 8;
+constexpr uint32_t kStreams = 16;
 
 class DeviceExecutor final : public Executor {
    public:
@@ -293,10 +293,16 @@ class DeviceExecutor final : public Executor {
         return e;
     }
 
-    // One quantum of one job on its own stream (cut into as many launches
-    // as the run needs).
+    // One quantum of one job (cut into as many launches as the run needs).
+    // Quanta take the pool's streams in turn: a job's previous quantum is
+    // complete when its next is queued, so it may run on any stream, and
+    // turning the streams over spreads long jobs across the hardware queues
+    // the streams map to (pinned to one stream, a few long jobs that shared
+    // a queue ran one after another while other queues idled).
     int queue_alone(Job& j, uint64_t t_end, uint32_t n) {
         Resident* r = res(j);
+        r->stream = streams_[next_stream_++ % kStreams];
+        sim_set_stream(r->sim, r->stream);
         r->last = r->stream;
         int rc = sim_run_async(r->sim, j.times.data() + j.next_time, n, t_end, r->pinned_rec);
         if (rc == ASEP_OK && hipEventRecord(r->done_ev, r->stream) != hipSuccess)
