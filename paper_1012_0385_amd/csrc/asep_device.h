@@ -899,6 +899,18 @@ __device__ uint32_t window_drift(const SimDesc& P, uint32_t sample, uint32_t cma
     }
 }
 
+// Sum of the positions 64 w + b of the particles (set bits b) of word w.
+__device__ __forceinline__ int64_t position_sum(uint64_t x, uint32_t w) {
+    const uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
+    uint32_t s = __popc(lo & 0xAAAAAAAAu) + __popc(hi & 0xAAAAAAAAu);
+    s += 2u * (__popc(lo & 0xCCCCCCCCu) + __popc(hi & 0xCCCCCCCCu));
+    s += 4u * (__popc(lo & 0xF0F0F0F0u) + __popc(hi & 0xF0F0F0F0u));
+    s += 8u * (__popc(lo & 0xFF00FF00u) + __popc(hi & 0xFF00FF00u));
+    s += 16u * (__popc(lo & 0xFFFF0000u) + __popc(hi & 0xFFFF0000u));
+    s += 32u * __popc(hi);
+    return (int64_t)s + 64 * (int64_t)w * (int64_t)__popcll(x);
+}
+
 // ---------------------------------------------------------------------------
 // The sweep kernel.  A workgroup serves either G whole rings (segs == 1:
 // the ring is periodic, measurements may be taken inside the launch) or one
@@ -922,6 +934,17 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
     constexpr bool FAST = V != kGeneric && V != kSca && !HALF;
     constexpr int AV = VarInfo<V>::A;
     constexpr int BV = VarInfo<V>::BB;
+    // Hop count of the single-lane cell loops (all but the sub-lattice
+    // update): a hop moves the particles' position sum M = sum_y y n_y by
+    // one in its direction, except a hop over the closing bond (L-1, 0),
+    // which moves it by -(L-1) (right) or L-1 (left).  So J = M(end) -
+    // M(start) + L X, with X the net right crossings of the closing bond.
+    // Cells are closed within a sub-sweep (their last bond is never
+    // tried), so X grows by the change in the particles the closing
+    // bond's slot holds to its right (sites 0 .. sig-1, its top sig bits):
+    // no work per attempt.  J below then counts X, and each lane adds the
+    // change in M of the words it owns.
+    constexpr bool WRAPJ = MODEL != kTwoLane && V != kSca;
 
     const uint32_t lb = blockIdx.x - P.wg_begin;
 
@@ -1034,6 +1057,19 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
             const uint64_t* src = P.words_in + (size_t)ring * NPL * nw;
             sa[i] = src[w];
             if (MODEL == kTwoLane) sb[i] = src[nw + w];
+        }
+    }
+    // position sum of the lane's own words at the start (frame 0)
+    int64_t Ms = 0;
+    if constexpr (WRAPJ) {
+#pragma unroll
+        for (int i = 0; i < C; ++i) {
+            const uint32_t pos = base_slot + (uint32_t)i;
+            if (i < cnt && (!seg || pos - lm < nout)) {
+                uint32_t w = base + pos;
+                if (w >= nw) w -= nw;
+                Ms += position_sum(sa[i], w);
+            }
         }
     }
     if (MODEL != kPlain && ring_ok) {
@@ -1176,9 +1212,22 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
             }
         }
         if (act) {
+            int64_t Jm = J;
+            if constexpr (WRAPJ) {
+                int64_t Mn = 0;
+#pragma unroll
+                for (int i = 0; i < C; ++i) {
+                    if (i < cnt) {
+                        uint32_t w = off + base_slot + (uint32_t)i;
+                        if (w >= nw) w -= nw;
+                        Mn += position_sum(sa[i], w);
+                    }
+                }
+                Jm = (int64_t)(64ull * nw) * J + Mn - Ms;
+            }
             atomicAdd(&red[gi * 4 + 0], (unsigned long long)ls1);
             atomicAdd(&red[gi * 4 + 1], (unsigned long long)ls2);
-            atomicAdd(&red[gi * 4 + 2], (unsigned long long)J);
+            atomicAdd(&red[gi * 4 + 2], (unsigned long long)Jm);
             atomicAdd(&red[gi * 4 + 3], (unsigned long long)ln);
         }
         __syncthreads();
@@ -1328,10 +1377,18 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
                             d += cell_ring_generic<MODEL == kDisorder>(xa, m0, m1, bb, lam, cc);
                     }
                 }
+                if constexpr (WRAPJ) {
+                    // the closing bond's slot (owned by exactly one window)
+                    if (w == nw - 1u && (!sg || pos - lm < nout)) {
+                        const uint64_t top = sig ? ~0ull << (64u - sig) : 0ull;
+                        dj += (int32_t)__popcll(xa & top) - (int32_t)__popcll(sa[i] & top);
+                    }
+                } else if (!sg || pos - lm < nout) {
+                    // a window counts the hops of the cells it owns
+                    dj += d;
+                }
                 sa[i] = xa;
                 if (MODEL == kTwoLane) sb[i] = xb;
-                // a window counts the hops of the cells it owns
-                if (!sg || pos - lm < nout) dj += d;
             }
         }
         J += dj;
@@ -1347,6 +1404,7 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
         sub_sweeps(std::integral_constant<int, 2>{});
     }
     shift_to(0, std::integral_constant<int, 0>{});
+    int64_t Me = 0;  // position sum of the lane's own words at the end
 #pragma unroll
     for (int i = 0; i < C; ++i) {
         if (i < cnt) {
@@ -1357,9 +1415,11 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
                 uint64_t* dst = P.words_out + (size_t)ring * NPL * nw;
                 dst[w] = sa[i];
                 if (MODEL == kTwoLane) dst[nw + w] = sb[i];
+                if constexpr (WRAPJ) Me += position_sum(sa[i], w);
             }
         }
     }
+    if constexpr (WRAPJ) J = (int64_t)(64ull * nw) * J + Me - Ms;
     // hops of the ring (whole ring) or of the window's own cells (segments)
     if (lt == 0 && gi < G) red[gi * 4 + 2] = 0;
     __syncthreads();
