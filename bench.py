@@ -43,9 +43,8 @@ PEAK_SLOTS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock: 32-bit VALU sl
 # flip of the two 32-bit halves of the word and the hop count (6 slots; a
 # cell of at most 32 sites flips within one 32-bit word: 5; byte fields, which
 # cells of 32 sites take, hold the offset where the shifts read it: one
-# fewer; a single lane takes its hop count from the closing bond's flux and
-# the particles' position sum, per sub-sweep rather than per attempt: one
-# fewer), plus one slot for extracting compared bits (b > 0), one for a
+# fewer; the hop count comes from the closing bond's flux and the particles'
+# position sum, per sub-sweep rather than per attempt: one fewer), plus one slot for extracting compared bits (b > 0), one for a
 # quenched mark and two for a second lane (its pair and the event decode).
 PHILOX_SLOTS = 40
 UPDATE_SLOTS = 6
@@ -108,8 +107,7 @@ def alu_slots_per_attempt(sim):
         upd -= 1  # a cell of at most 32 sites flips within one 32-bit word
     if byte_fields:
         upd -= 1  # the offset is the low bits of its byte, read by the shifts
-    if not two:
-        upd -= 1  # no hop count per attempt
+    upd -= 1  # no hop count per attempt
     return PHILOX_SLOTS * nblk / a + upd
 
 

@@ -518,11 +518,11 @@ __device__ __forceinline__ int32_t cell_two_lane_generic(uint64_t& xa, uint64_t&
 // the hop is one masked XOR per half of the hopping lane's word, and only
 // lane-change candidates (rare) take a branch for their draw.
 template <int A, int BB, int NA>
-__device__ __forceinline__ int32_t cell_two_lane_fast(uint64_t& xa, uint64_t& xb, uint64_t tm,
-                                                       const CellCtx& c) {
+__device__ __forceinline__ void cell_two_lane_fast(uint64_t& xa, uint64_t& xb, uint64_t tm,
+                                                    const CellCtx& c) {
     constexpr int PER = 4 * A;
     constexpr int NB = (NA + PER - 1) / PER;
-    int32_t dj = 0;
+    int32_t dj = 0;  // not returned: the sweep counts hops at the closing bond
     ChangeDraws cd;
     change_begin_bits(cd, c);
     bool over = false;
@@ -563,10 +563,6 @@ __device__ __forceinline__ int32_t cell_two_lane_fast(uint64_t& xa, uint64_t& xb
                          xor_masked((uint32_t)xa, (uint32_t)M, FA);
                     xb = ((uint64_t)xor_masked((uint32_t)(xb >> 32), (uint32_t)(M >> 32), FB) << 32) |
                          xor_masked((uint32_t)xb, (uint32_t)M, FB);
-                    dj += (int32_t)FB - (int32_t)FA;  // A right: +1, B left: -1
-                    // add now: summed later, every attempt's outcome would
-                    // stay live across the lane-change branches below
-                    asm volatile("" : "+v"(dj));
                     if (FC) {
                         // the next of the four decisions made up front (a
                         // fifth candidate sends the cell to the replay)
@@ -592,9 +588,8 @@ __device__ __forceinline__ int32_t cell_two_lane_fast(uint64_t& xa, uint64_t& xb
     if (over) {  // a fifth lane-change candidate: redo the cell exactly
         xa = xa0;
         xb = xb0;
-        dj = cell_two_lane_generic(xa, xb, tm, 0, 6, c);
+        cell_two_lane_generic(xa, xb, tm, 0, 6, c);
     }
-    return dj;
 }
 
 // The paper's two-sub-lattice update (Sec. 2.1, Fig. parasep) on one slot:
@@ -934,17 +929,19 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
     constexpr bool FAST = V != kGeneric && V != kSca && !HALF;
     constexpr int AV = VarInfo<V>::A;
     constexpr int BV = VarInfo<V>::BB;
-    // Hop count of the single-lane cell loops (all but the sub-lattice
-    // update): a hop moves the particles' position sum M = sum_y y n_y by
-    // one in its direction, except a hop over the closing bond (L-1, 0),
-    // which moves it by -(L-1) (right) or L-1 (left).  So J = M(end) -
-    // M(start) + L X, with X the net right crossings of the closing bond.
-    // Cells are closed within a sub-sweep (their last bond is never
+    // Hop count of the cell loops (all but the sub-lattice update): a hop
+    // moves the particles' position sum M = sum_y y n_y by one in its
+    // direction, except a hop over the closing bond (L-1, 0), which moves
+    // it by -(L-1) (right) or L-1 (left).  So J = M(end) - M(start) + L X,
+    // with X the net right crossings of the closing bond.  Two lanes: J
+    // (A hops right minus B hops left) is the displacement of all
+    // particles, M and X summed over both lanes; a lane change keeps the
+    // sum.  Cells are closed within a sub-sweep (their last bond is never
     // tried), so X grows by the change in the particles the closing
     // bond's slot holds to its right (sites 0 .. sig-1, its top sig bits):
     // no work per attempt.  J below then counts X, and each lane adds the
     // change in M of the words it owns.
-    constexpr bool WRAPJ = MODEL != kTwoLane && V != kSca;
+    constexpr bool WRAPJ = V != kSca;
 
     const uint32_t lb = blockIdx.x - P.wg_begin;
 
@@ -1069,6 +1066,7 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
                 uint32_t w = base + pos;
                 if (w >= nw) w -= nw;
                 Ms += position_sum(sa[i], w);
+                if (MODEL == kTwoLane) Ms += position_sum(sb[i], w);
             }
         }
     }
@@ -1221,6 +1219,7 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
                         uint32_t w = off + base_slot + (uint32_t)i;
                         if (w >= nw) w -= nw;
                         Mn += position_sum(sa[i], w);
+                        if (MODEL == kTwoLane) Mn += position_sum(sb[i], w);
                     }
                 }
                 Jm = (int64_t)(64ull * nw) * J + Mn - Ms;
@@ -1364,7 +1363,7 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
                 } else if constexpr (FAST) {
                     cc.k = w;
                     if (MODEL == kTwoLane)
-                        d = cell_two_lane_fast<AV, BV, 64>(xa, xb, m0, cc);
+                        cell_two_lane_fast<AV, BV, 64>(xa, xb, m0, cc);
                     else
                         d = cell_ring_fast<AV, BV, Q0, MODEL == kDisorder, 16>(xa, m0, m1, cc);
                 } else {
@@ -1382,6 +1381,8 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
                     if (w == nw - 1u && (!sg || pos - lm < nout)) {
                         const uint64_t top = sig ? ~0ull << (64u - sig) : 0ull;
                         dj += (int32_t)__popcll(xa & top) - (int32_t)__popcll(sa[i] & top);
+                        if (MODEL == kTwoLane)
+                            dj += (int32_t)__popcll(xb & top) - (int32_t)__popcll(sb[i] & top);
                     }
                 } else if (!sg || pos - lm < nout) {
                     // a window counts the hops of the cells it owns
@@ -1415,7 +1416,10 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
                 uint64_t* dst = P.words_out + (size_t)ring * NPL * nw;
                 dst[w] = sa[i];
                 if (MODEL == kTwoLane) dst[nw + w] = sb[i];
-                if constexpr (WRAPJ) Me += position_sum(sa[i], w);
+                if constexpr (WRAPJ) {
+                    Me += position_sum(sa[i], w);
+                    if (MODEL == kTwoLane) Me += position_sum(sb[i], w);
+                }
             }
         }
     }
