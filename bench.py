@@ -57,9 +57,9 @@ UPDATE_SLOTS = 6
 # only for the kernel sources they were taken on (SHA-256 prefix below) and
 # for that launch shape; otherwise the bench reports traffic as unknown.
 SWEEP_TRAFFIC = {
-    "src_sha256": "850c3303bbe66141",
+    "src_sha256": "f63747ed831ffee8",
     "launch_shape": {"windows": 4, "window_sweeps": 255, "rings_per_wg": 0},
-    "fetch_kib": 855.16,   # KPZ 853.41, EW 856.91
+    "fetch_kib": 858.15,   # KPZ 858.4, EW 857.9
     "write_kib": 1032.0,
     "fetch_scale": 2.0,    # 4 GiB copy: FETCH_SIZE 2097206 KiB
     "write_scale": 1.0,    # 4 GiB copy: WRITE_SIZE 4194304 KiB
