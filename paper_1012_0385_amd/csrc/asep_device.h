@@ -527,6 +527,11 @@ __device__ __forceinline__ void cell_two_lane_fast(uint64_t& xa, uint64_t& xb, u
     change_begin_bits(cd, c);
     bool over = false;
     const uint64_t xa0 = xa, xb0 = xb;
+    // the outcome table's low half in a vector register for the select
+    // below (two scalar operands do not fit one instruction; held here, it
+    // is not copied again for every attempt)
+    uint32_t lut_lo = (uint32_t)c.lut2;
+    asm volatile("" : "+v"(lut_lo));
 #pragma unroll
     for (int blk = 0; blk < NB; ++blk) {
         const Blk r = philox(c.k, c.glo, c.c2b | ((uint32_t)blk << 16), c.sample, c.k0, c.k1);
@@ -543,16 +548,19 @@ __device__ __forceinline__ void cell_two_lane_fast(uint64_t& xa, uint64_t& xb, u
                     // of e1, the turning bit at j, the pair mask
                     const uint32_t E0 = (uint32_t)__builtin_amdgcn_sbfe((int32_t)u, sh, 1);
                     const uint32_t E1 = (uint32_t)__builtin_amdgcn_sbfe((int32_t)u, sh + 1u, 1);
-                    const uint32_t lw = (uint32_t)(c.lut2 >> (bfe(u, sh + 1u, 1) << 5));
+                    // E1 ? high half : low half (truth table 0xCA: src0 selects)
+                    const uint32_t lw = __builtin_amdgcn_bitop3_b32(
+                        E1, (uint32_t)(c.lut2 >> 32), lut_lo, 0xCA);
                     const uint32_t TT =
                         (uint32_t)__builtin_amdgcn_sbfe((int32_t)(uint32_t)(tm >> j), 0, 1);
-                    const uint32_t eh = sh >= 4u ? u >> (sh - 4u) : u << (4u - sh);
                     const uint64_t M = 3ull << j;
                     // the state chain: both lanes' pairs, then one table bit
+                    // (offset bits 0-3 the pairs, bit 4 the event's low bit
+                    // from the mask E0; v_bfe reads five offset bits)
                     const int64_t sa = (int64_t)xa >> j;
                     const int64_t sb = (int64_t)xb >> j;
                     const uint32_t v = insert_low2((uint32_t)sa, (uint32_t)sb << 2);
-                    const uint32_t idx = __builtin_amdgcn_bitop3_b32(v, eh, 0xFu, 0xE4);
+                    const uint32_t idx = __builtin_amdgcn_bitop3_b32(v, E0, 0xFu, 0xE4);
                     const uint32_t F = (uint32_t)__builtin_amdgcn_sbfe((int32_t)lw, idx, 1);
                     // F & ~E0 & ~E1, F & E0 & ~E1, F & E1 & TT (the table
                     // index of a three-input op is src0 << 2 | src1 << 1 | src2)
