@@ -572,12 +572,18 @@ __device__ __forceinline__ void cell_two_lane_fast(uint64_t& xa, uint64_t& xb, u
                     xb = ((uint64_t)xor_masked((uint32_t)(xb >> 32), (uint32_t)(M >> 32), FB) << 32) |
                          xor_masked((uint32_t)xb, (uint32_t)M, FB);
                     if (FC) {
-                        // the next of the four decisions made up front (a
-                        // fifth candidate sends the cell to the replay)
-                        const bool acc = change_accept<false>(cd, c, over);
-                        const uint64_t m1 = acc ? 1ull << j : 0ull;
-                        xa ^= m1;
-                        xb ^= m1;
+                        // the next of the four decisions made up front as
+                        // a mask (a fifth candidate finds the sentinel and
+                        // sends the cell to the replay), then the site's
+                        // bit flips in both lanes under it
+                        over |= cd.m == 1;
+                        const uint32_t am = (uint32_t)__builtin_amdgcn_sbfe(cd.m, 0, 1);
+                        cd.m >>= 1;
+                        const uint64_t B = 1ull << j;
+                        xa = ((uint64_t)xor_masked((uint32_t)(xa >> 32), (uint32_t)(B >> 32), am) << 32) |
+                             xor_masked((uint32_t)xa, (uint32_t)B, am);
+                        xb = ((uint64_t)xor_masked((uint32_t)(xb >> 32), (uint32_t)(B >> 32), am) << 32) |
+                             xor_masked((uint32_t)xb, (uint32_t)B, am);
                     }
                 } else {
                     const uint32_t b = BB >= 0 ? (uint32_t)BB : c.b;
