@@ -1336,6 +1336,15 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
         // past nout + nsub - t can no longer reach the output (nor are they
         // owned).  A wave whose first slot is there skips its attempts.
         const bool live = !sg || t < tlive;
+        // Wave-uniform rings, several slots per lane: whether this wave's
+        // slots (words wb of its first lane onwards, 64 C of them) hold the
+        // ring's last word, one scalar test per sub-sweep instead of one per
+        // slot (with one slot per lane the test would only add work)
+        bool wrap_wave = true;
+        if constexpr (WRAPJ && WU && C > 1) {
+            const uint32_t wbw = __builtin_amdgcn_readfirstlane(wb);
+            wrap_wave = nw - 1u - wbw < 64u * (uint32_t)C;
+        }
 #pragma unroll
         for (int i = 0; i < C; ++i) {
             if (live && i < cnt) {
@@ -1392,11 +1401,13 @@ __device__ __forceinline__ void sweep_body(const SimDesc& P) {
                 }
                 if constexpr (WRAPJ) {
                     // the closing bond's slot (owned by exactly one window)
-                    if (w == nw - 1u && (!sg || pos - lm < nout)) {
-                        const uint64_t top = sig ? ~0ull << (64u - sig) : 0ull;
-                        dj += (int32_t)__popcll(xa & top) - (int32_t)__popcll(sa[i] & top);
-                        if (MODEL == kTwoLane)
-                            dj += (int32_t)__popcll(xb & top) - (int32_t)__popcll(sb[i] & top);
+                    if (wrap_wave) {
+                        if (w == nw - 1u && (!sg || pos - lm < nout)) {
+                            const uint64_t top = sig ? ~0ull << (64u - sig) : 0ull;
+                            dj += (int32_t)__popcll(xa & top) - (int32_t)__popcll(sa[i] & top);
+                            if (MODEL == kTwoLane)
+                                dj += (int32_t)__popcll(xb & top) - (int32_t)__popcll(sb[i] & top);
+                        }
                     }
                 } else if (!sg || pos - lm < nout) {
                     // a window counts the hops of the cells it owns
