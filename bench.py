@@ -57,7 +57,7 @@ UPDATE_SLOTS = 6
 # only for the kernel sources they were taken on (SHA-256 prefix below) and
 # for that launch shape; otherwise the bench reports traffic as unknown.
 SWEEP_TRAFFIC = {
-    "src_sha256": "f63747ed831ffee8",
+    "src_sha256": "b09b9092d30e23f9",
     "launch_shape": {"windows": 4, "window_sweeps": 255, "rings_per_wg": 0},
     "fetch_kib": 858.15,   # KPZ 858.4, EW 857.9
     "write_kib": 1032.0,
