@@ -106,6 +106,22 @@ def test_many_rings_per_workgroup(orc):
     compare(orc, dict(L=320, p=1.0, q=0.0, seed=5, stream=9, sample_offset=1000), [0, 30], 70)
 
 
+@pytest.mark.parametrize("kw", [
+    dict(L=64, p=1.0, q=0.0, cell_log2=5, subsweeps=2),                 # byte fields, q = 0
+    dict(L=64, p=0.5, q=0.5, cell_log2=5, subsweeps=2, init=1),         # byte fields, one bit
+    dict(L=64, p=0.8, q=0.3, cell_log2=4, subsweeps=4),                 # generic loop
+    dict(L=64, p=1.0, q=0.25, cell_log2=5, subsweeps=2, slow_frac=0.3, slow_factor=0.5),
+    dict(L=64, model=1, init=1, density=0.4, p=1.0, q=1.0, lane_rate=0.5, turn_frac=0.3,
+         cell_log2=5, subsweeps=8),                                     # two lanes
+    dict(L=128, p=0.5, q=0.5, cell_log2=5, subsweeps=2, init=1),
+])
+def test_one_and_two_word_rings(orc, kw):
+    # every frame puts the closing bond (L-1, 0) inside the ring's last slot,
+    # which here is also its first: the hop count taken at that bond and from
+    # the position sums must still equal the oracle's count of hops
+    compare(orc, dict(seed=12, stream=3, **kw), [0, 1, 2, 7, 50, 333], 70)
+
+
 def test_disorder(orc):
     kw = dict(L=4096, p=1.0, q=0.0, slow_frac=0.1, slow_factor=0.5, samples_per_disorder=4,
               seed=3, stream=2)
